@@ -1,0 +1,109 @@
+"""Oracle Metropolis-Hastings and delayed-acceptance steps (FP64, CPU).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Sec. 2, Algorithm 1: draw a proposal from a symmetric kernel k(x_k, .),
+accept it with probability min(1, exp(Phi(x_k) - Phi(x_bar))), otherwise
+stay.  Proposals are Gaussian random-walk steps in the sampling coordinates
+phi = (a, b, ln gamma, ln d); the prior is uniform on a box in phi, so inside
+the box the prior ratio is 1 (the acceptance formula of Algorithm 1 is exact)
+and a proposal outside the box has zero posterior density and is rejected
+without evaluating Phi.
+
+Random numbers follow the sampler's counter-based contract (Philox4x32-10,
+key = (chain, seed), counter = (step, purpose, block)):
+purpose 0 = proposal normals, 1 = final accept uniform, 2 = first-stage
+(surrogate) uniform.  Accept iff log U < log alpha.
+
+The delayed-acceptance step (Christen and Fox, J. Comput. Graph. Stat. 14(4),
+2005) screens a proposal with a cheap approximation Phi~ first:
+  stage 1: accept iff log U1 < Phi~(x) - Phi~(y);
+  stage 2 (only if stage 1 accepts): accept iff
+           log U2 < [Phi(x) - Phi(y)] - [Phi~(x) - Phi~(y)],
+which leaves the exact posterior invariant for a symmetric proposal.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import normals4, uniform1
+
+PURPOSE_PROPOSAL = 0
+PURPOSE_ACCEPT = 1
+PURPOSE_STAGE1 = 2
+
+
+def propose(phi, seed, chain, step, step_sd, free_mask):
+    """phi' = phi + s .* z on the free coordinates (Algorithm 1, first step)."""
+    z = normals4(seed, chain, step, PURPOSE_PROPOSAL)
+    prop = np.array(phi, dtype=np.float64).copy()
+    for i in range(4):
+        if (free_mask >> i) & 1:
+            prop[i] = prop[i] + step_sd[i] * z[i]
+    return prop
+
+
+def in_box(phi, lo, hi) -> bool:
+    return all(lo[i] <= phi[i] <= hi[i] for i in range(4))
+
+
+def rwm_step(phi, loglik, seed, chain, step, lo, hi, step_sd, free_mask, loglik_fn):
+    """One step of Algorithm 1 for one chain.
+
+    Returns (phi_next, loglik_next, accepted, solved)."""
+    prop = propose(phi, seed, chain, step, step_sd, free_mask)
+    if not in_box(prop, lo, hi):
+        return np.array(phi, dtype=np.float64), loglik, False, False
+    ll_prop = float(loglik_fn(prop))
+    u = uniform1(seed, chain, step, PURPOSE_ACCEPT)
+    log_alpha = loglik - ll_prop
+    if math.log(u) < log_alpha:
+        return prop, ll_prop, True, True
+    return np.array(phi, dtype=np.float64), loglik, False, True
+
+
+def rwm_batch_step(phis, logliks, seed, step, lo, hi, step_sd, free_mask, loglik_batch_fn):
+    """Algorithm 1 applied to every chain; loglik_batch_fn maps [m,4] -> [m].
+
+    Returns (phis, logliks, accepted[bool], solved[bool])."""
+    phis = np.array(phis, dtype=np.float64)
+    logliks = np.array(logliks, dtype=np.float64)
+    C = phis.shape[0]
+    props = np.stack([propose(phis[c], seed, c, step, step_sd, free_mask) for c in range(C)])
+    inside = np.array([in_box(props[c], lo, hi) for c in range(C)])
+    ll_prop = np.full(C, np.inf)
+    if inside.any():
+        ll_prop[inside] = loglik_batch_fn(props[inside])
+    accepted = np.zeros(C, dtype=bool)
+    for c in range(C):
+        if not inside[c]:
+            continue
+        u = uniform1(seed, c, step, PURPOSE_ACCEPT)
+        if math.log(u) < logliks[c] - ll_prop[c]:
+            accepted[c] = True
+    phis[accepted] = props[accepted]
+    logliks[accepted] = ll_prop[accepted]
+    return phis, logliks, accepted, inside
+
+
+def da_step(phi, loglik, loglik_sur, seed, chain, step, lo, hi, step_sd, free_mask,
+            loglik_fn, surrogate_fn):
+    """One delayed-acceptance step for one chain.
+
+    Returns (phi, loglik, loglik_sur, accepted1, accepted, solved)."""
+    prop = propose(phi, seed, chain, step, step_sd, free_mask)
+    keep = (np.array(phi, dtype=np.float64), loglik, loglik_sur)
+    if not in_box(prop, lo, hi):
+        return (*keep, False, False, False)
+    sur_prop = float(surrogate_fn(prop))
+    u1 = uniform1(seed, chain, step, PURPOSE_STAGE1)
+    if not math.log(u1) < loglik_sur - sur_prop:
+        return (*keep, False, False, False)
+    ll_prop = float(loglik_fn(prop))
+    u2 = uniform1(seed, chain, step, PURPOSE_ACCEPT)
+    log_alpha2 = (loglik - ll_prop) - (loglik_sur - sur_prop)
+    if math.log(u2) < log_alpha2:
+        return prop, ll_prop, sur_prop, True, True, True
+    return (*keep, True, False, True)

@@ -1,0 +1,436 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by mathematics.
+
+None of these re-run the oracle's own formula: each checks it against a
+closed form, an invariant, a printed value, a published test vector or an
+independent algorithm (dense elimination), chosen so that a dropped term, a
+wrong sign, a wrong index or a swapped operand fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sampler as osamp
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def cos_mode(n, k, l):
+    i = np.arange(n)
+    cx = np.cos(k * np.pi * (i + 0.5) / n)
+    cy = np.cos(l * np.pi * (i + 0.5) / n)
+    return np.outer(cy, cx)  # [j, i]
+
+
+def lam1(n, k):
+    return 4.0 * n * n * math.sin(k * math.pi / (2 * n)) ** 2
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10: known-answer vectors published with the Random123 library
+# (Salmon et al., SC 2011).
+
+def test_philox_known_answers():
+    cases = [
+        ([0, 0, 0, 0], [0, 0], [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]),
+        ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2, [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]),
+        ([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0],
+         [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]),
+    ]
+    for ctr, key, want in cases:
+        assert list(oracle.philox4x32_10(ctr, key)) == want
+
+
+def test_uniform_from_words_range_and_exactness():
+    assert oracle.uniform_from_words(0, 0) == 0.5 * 2.0 ** -52
+    top = oracle.uniform_from_words(0xFFFFFFFF, 0xFFFFFFFF)
+    assert top < 1.0 and top == 1.0 - 0.5 * 2.0 ** -52
+    assert oracle.uniform_from_words(0x80000000, 0) == 0.5 + 0.5 * 2.0 ** -52
+
+
+def test_normals_and_uniforms_distribution():
+    z = np.array([oracle.normals4(7, c, s, 0) for c in range(50) for s in range(100)]).ravel()
+    assert abs(z.mean()) < 4 / math.sqrt(z.size)
+    assert abs(z.var() - 1) < 4 * math.sqrt(2 / z.size)
+    from scipy import stats
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+    u = np.array([oracle.uniform1(7, c, s, 1) for c in range(50) for s in range(100)])
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+    # different purposes / chains / steps give different streams
+    assert oracle.uniform1(7, 0, 0, 1) != oracle.uniform1(7, 0, 0, 2)
+    assert oracle.uniform1(7, 0, 0, 1) != oracle.uniform1(7, 1, 0, 1)
+    assert oracle.uniform1(7, 0, 0, 1) != oracle.uniform1(7, 0, 1, 1)
+
+
+# --------------------------------------------------------------------------
+# Grid operator (Sec. 3.1.1: 5-point stencil, Neumann boundary)
+
+@pytest.mark.parametrize("n", [4, 7, 32])
+def test_laplacian_dct_eigenvectors(n):
+    """cos(k pi (i+1/2)/n) cos(l pi (j+1/2)/n) are the eigenvectors of the
+    mirror-ghost 5-point Laplacian, eigenvalue -(lam_k + lam_l) with
+    lam_k = (4/h^2) sin^2(k pi / 2n)."""
+    for k, l in [(0, 0), (1, 0), (0, 2), (3, 1), (n - 1, n - 1)]:
+        w = cos_mode(n, k, l)
+        lap = oracle.laplacian(w)
+        want = -(lam1(n, k) + lam1(n, l)) * w
+        # rounding of the test modes and of the 5-term sum, scaled by 1/h^2
+        scale = 8.0 * n * n * np.abs(w).max()
+        assert np.abs(lap - want).max() <= 32 * np.finfo(float).eps * scale
+
+
+def test_laplacian_symmetric_and_conservative():
+    rng = np.random.default_rng(0)
+    n = 9
+    a, b = rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    la, lb = oracle.laplacian(a), oracle.laplacian(b)
+    assert abs((la * b).sum() - (a * lb).sum()) < 1e-10 * np.abs(la).sum()
+    # zero row sums (constants are in the kernel) and zero column sums (mass)
+    assert np.abs(oracle.laplacian(np.full((n, n), 3.0))).max() == 0.0
+    assert abs(la.sum()) < 1e-10 * np.abs(la).sum()
+
+
+def test_apply_A_definition_on_modes():
+    n = 8
+    w = cos_mode(n, 2, 3)
+    sig = np.full((n, n), 5.0)
+    got = oracle.apply_A(sig, 0.3, w)
+    assert np.allclose(got, (5.0 + 0.3 * (lam1(n, 2) + lam1(n, 3))) * w, rtol=1e-13, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Conjugate gradients against an independent direct solve
+
+@pytest.mark.parametrize("n,c", [(2, 0.7), (5, 0.01), (8, 1.0)])
+def test_cg_matches_dense_elimination(n, c):
+    rng = np.random.default_rng(n)
+    sig = rng.uniform(0.5, 3.0, (n, n))
+    b = rng.standard_normal((n, n))
+    x_lu, st = oracle.dense_solve(sig, c, b)
+    assert st == 0
+    # residual of the dense solution is tiny (independent of CG)
+    assert np.abs(oracle.apply_A(sig, c, x_lu) - b).max() < 1e-10
+    x_cg, it, st = oracle.cg(sig, c, b, np.zeros_like(b), rtol=1e-14)
+    assert st == 0 and it <= 10 * n * n
+    assert np.abs(x_cg - x_lu).max() <= 1e-10 * np.abs(x_lu).max()
+
+
+def test_cg_single_mode_one_iteration():
+    n = 16
+    w = cos_mode(n, 3, 5)
+    sig = np.full((n, n), 2.0)
+    c = 0.05
+    x, it, st = oracle.cg(sig, c, w, np.zeros_like(w), rtol=1e-12)
+    want = w / (2.0 + c * (lam1(n, 3) + lam1(n, 5)))
+    assert st == 0 and it == 1
+    assert np.abs(x - want).max() < 1e-14
+
+
+def test_cg_flags():
+    n = 6
+    b = np.random.default_rng(1).standard_normal((n, n))
+    # indefinite operator: negative sigma everywhere -> p.Ap <= 0 at once
+    _, _, st = oracle.cg(np.full((n, n), -1e6), 1e-3, b, np.zeros_like(b))
+    assert st & oracle.BREAKDOWN
+    # iteration cap
+    _, it, st = oracle.cg(np.full((n, n), 1.0), 1.0, b, np.zeros_like(b), rtol=1e-14, maxit=1)
+    assert st & oracle.NOT_CONVERGED and it == 1
+    # non-finite input
+    bb = b.copy()
+    bb[2, 3] = np.nan
+    _, _, st = oracle.cg(np.full((n, n), 1.0), 1.0, bb, np.zeros_like(b))
+    assert st & oracle.NONFINITE
+
+
+# --------------------------------------------------------------------------
+# Kinetics and steady state (eq. (reactions), Table 1, eq. (ic_numerical))
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([float(x) for x in line.split()])
+    return rows
+
+
+def test_printed_steady_state_matches_kinetics():
+    """The paper prints u*, v* for Table 1 and for Example 1; the zero of the
+    kinetics f = a - u + u^2 v, g = b - u^2 v must reproduce them."""
+    for a, b, us_p, vs_p, dec in _golden_rows("table1_steady_state.txt"):
+        # solve f = g = 0: adding gives u = a + b, then v = b / u^2
+        us = a + b
+        vs = b / us ** 2
+        assert abs(a - us + us * us * vs) < 1e-15 and abs(b - us * us * vs) < 1e-15
+        assert round(us, int(dec)) == pytest.approx(us_p, abs=0.6 * 10 ** -dec)
+        assert round(vs, int(dec)) == pytest.approx(vs_p, abs=0.6 * 10 ** -dec)
+
+
+def test_turing_conditions_printed_form():
+    """eq. (turing) entries equal the Jacobian of the kinetics at the steady state."""
+    for a, b, d, tr, det, dfg, disc in _golden_rows("turing_conditions.txt"):
+        us, vs = a + b, b / (a + b) ** 2
+        fu, fv = -1 + 2 * us * vs, us * us
+        gu, gv = -2 * us * vs, -us * us
+        assert fu + gv == pytest.approx(tr, abs=1e-12)
+        assert fu * gv - fv * gu == pytest.approx(det, abs=1e-12)
+        assert d * fu + gv == pytest.approx(dfg, abs=1e-12)
+        assert (d * fu + gv) ** 2 - 4 * d * (fu * gv - fv * gu) == pytest.approx(disc, abs=1e-12)
+
+
+def test_homogeneous_steady_state_is_fixed():
+    for theta in [(0.1, 0.9, 200.0, 10.0), (0.126779, 0.792366, 1000.0, 10.0), (0.3, 0.6, 70.0, 5.0)]:
+        a, b = theta[:2]
+        n = 8
+        u0 = np.full((n, n), a + b)
+        v0 = np.full((n, n), b / (a + b) ** 2)
+        u, v, it, st = oracle.forward_solve(theta, u0, v0, 2.5e-4, 50, rtol=1e-13)
+        assert st == 0
+        assert np.abs(u - u0).max() < 1e-12 and np.abs(v - v0).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Linearised IMEX dynamics: the exact discrete dispersion relation
+
+def imex_mode_matrix(theta, lam, tau, rate=0.0, m=2.0):
+    """Linearisation of one IMEX step about (u*, v*) for a Laplacian
+    eigenmode with -Lap eigenvalue lam (derived by hand from the scheme:
+    perturb u^n, v^n in the two implicit equations and keep first order)."""
+    a, b, g, d = theta
+    us, vs = a + b, b / (a + b) ** 2
+    al_u = 1 / tau + m * rate + g * (1 - us * vs) + lam
+    al_v = 1 / tau + m * rate + g * us * us + d * lam
+    return np.array([[(1 / tau + g * us * vs) / al_u, g * us * us / al_u],
+                     [-2 * g * us * vs / al_v, (1 / tau) / al_v]])
+
+
+def continuous_rate(theta, lam):
+    """Largest real part of eig(gamma J - lam diag(1, d)), J from eq. (turing)."""
+    a, b, g, d = theta
+    us, vs = a + b, b / (a + b) ** 2
+    J = np.array([[-1 + 2 * us * vs, us * us], [-2 * us * vs, -us * us]])
+    return np.linalg.eigvals(g * J - lam * np.diag([1.0, d])).real.max()
+
+
+@pytest.mark.parametrize("k,l,theta,tau", [
+    (2, 2, (0.1, 0.9, 200.0, 10.0), 2.5e-4),
+    (1, 3, (0.1, 0.9, 200.0, 10.0), 2.5e-4),
+    (0, 0, (0.1, 0.9, 200.0, 10.0), 2.5e-3),
+    (5, 0, (0.2, 0.7, 300.0, 20.0), 1e-3),
+])
+def test_small_mode_growth_matches_discrete_dispersion(k, l, theta, tau):
+    n, steps, eps = 16, 12, 1e-4
+    a, b = theta[:2]
+    us, vs = a + b, b / (a + b) ** 2
+    phi = cos_mode(n, k, l)
+    lam = lam1(n, k) + lam1(n, l)
+    cu, cv = 1.0, -0.5
+    amps = []
+    for sgn in (+1, -1):
+        u, v, _, st = oracle.forward_solve(theta, us + sgn * eps * cu * phi,
+                                           vs + sgn * eps * cv * phi, tau, steps, rtol=1e-15)
+        assert st == 0
+        amps.append(np.array([((u - us) * phi).sum(), ((v - vs) * phi).sum()]) / (phi * phi).sum())
+    got = 0.5 * (amps[0] - amps[1])  # odd part: cancels the quadratic response
+    want = np.linalg.matrix_power(imex_mode_matrix(theta, lam, tau), steps) @ np.array([cu, cv]) * eps
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+
+
+def test_discrete_dispersion_tends_to_turing_growth_rate():
+    """log spectral radius / tau of the IMEX mode map -> the continuous rate."""
+    theta = (0.1, 0.9, 200.0, 10.0)
+    lam = 2 * lam1(32, 2)
+    rates = []
+    for tau in (1e-4, 1e-5, 1e-6):
+        ev = np.linalg.eigvals(imex_mode_matrix(theta, lam, tau))
+        rates.append(math.log(np.abs(ev).max()) / tau)
+    cont = continuous_rate(theta, lam)
+    assert cont > 0  # this mode lies inside the Turing band
+    errs = [abs(r - cont) for r in rates]
+    assert errs[2] < 0.01 * abs(cont) and errs[0] > errs[1] > errs[2]
+
+
+def test_no_growth_outside_turing_space():
+    """d = 1 violates d f_u + g_v > 0: every mode decays (continuous and scheme)."""
+    theta = (0.1, 0.9, 200.0, 1.0)
+    n = 16
+    u0, v0 = oracle_ic(n, theta, rel=1e-3)
+    u, v, _, st = oracle.forward_solve(theta, u0, v0, 2.5e-4, 400, rtol=1e-12)
+    assert st == 0
+    assert np.abs(u - 1.0).max() < np.abs(u0 - 1.0).max()
+    for k in range(1, 8):
+        assert continuous_rate(theta, lam1(n, k)) < 0
+        assert np.abs(np.linalg.eigvals(imex_mode_matrix(theta, lam1(n, k), 2.5e-4))).max() < 1
+
+
+def test_homogeneous_mode_stability_bound():
+    """The Picard-linearised step is unstable for the k = 0 mode when
+    gamma tau > |f_u + g_v| / ((a+b)(2b - a)); at theta = (0.1, 0.9) that is
+    0.1176..., so dt = 2.5e-3 (gamma tau = 0.5) and 1e-3 (0.2) at gamma = 200
+    grow and 2.5e-4 (0.05) decays.  Checked on the nonlinear oracle."""
+    theta = (0.1, 0.9, 200.0, 10.0)
+    a, b = theta[:2]
+    bound = 0.2 / ((a + b) * (2 * b - a))
+    assert bound == pytest.approx(0.11764705882, rel=1e-9)
+    for tau, grows, steps in ((2.5e-3, True, 50), (1e-3, True, 500), (2.5e-4, False, 900)):
+        rad = np.abs(np.linalg.eigvals(imex_mode_matrix(theta, 0.0, tau))).max()
+        assert (rad > 1) == grows
+        assert (rad ** steps > 100) if grows else (rad ** steps < 0.1)
+        n = 4
+        u0, v0 = np.full((n, n), 1.0 + 1e-6), np.full((n, n), 0.9)
+        u, v, _, st = oracle.forward_solve(theta, u0, v0, tau, steps, rtol=1e-14)
+        assert st == 0
+        gain = math.hypot(np.abs(u - 1.0).max(), np.abs(v - 0.9).max()) / 1e-6
+        assert (gain > 10) if grows else (gain < 1)
+
+
+# --------------------------------------------------------------------------
+# Conservation (gamma = 0) and the growing domain (Sec. 3.1)
+
+def test_mass_conservation_without_reaction():
+    theta = (0.1, 0.9, 0.0, 10.0)
+    n = 12
+    rng = np.random.default_rng(3)
+    u0, v0 = 1 + 0.1 * rng.standard_normal((n, n)), 1 + 0.1 * rng.standard_normal((n, n))
+    u, v, _, st = oracle.forward_solve(theta, u0, v0, 1e-3, 30, rtol=1e-14)
+    assert st == 0
+    assert abs(u.sum() - u0.sum()) < 1e-10 and abs(v.sum() - v0.sum()) < 1e-10
+    # diffusion smooths
+    assert u.std() < u0.std()
+
+
+def test_growing_domain_dilution_and_diffusivity():
+    """gamma = 0 on rho = exp(r t): sum(u^{n+1}) (1 + tau m r) = sum(u^n) with
+    m = 2, and a cosine mode decays by (1/tau) / (1/tau + m r + lam rho_n^-2)."""
+    theta = (0.1, 0.9, 0.0, 3.0)
+    n, tau, rate, steps = 16, 1e-3, 0.4, 25
+    phi = cos_mode(n, 2, 1)
+    lam = lam1(n, 2) + lam1(n, 1)
+    u0 = 1.0 + 0.01 * phi
+    v0 = 2.0 + 0.01 * phi
+    u, v, _, st = oracle.forward_solve(theta, u0, v0, tau, steps, growth=1, rate=rate, rtol=1e-15)
+    assert st == 0
+    mass = (1 + tau * 2 * rate) ** -steps
+    assert u.sum() == pytest.approx(u0.sum() * mass, rel=1e-12)
+    amp_u, amp_v = 0.01, 0.01
+    for s in range(steps):
+        inv_rho2 = math.exp(-2 * rate * s * tau)
+        amp_u *= (1 / tau) / (1 / tau + 2 * rate + lam * inv_rho2)
+        amp_v *= (1 / tau) / (1 / tau + 2 * rate + 3.0 * lam * inv_rho2)
+    got_u = ((u - u.mean()) * phi).sum() / (phi * phi).sum()
+    got_v = ((v - v.mean()) * phi).sum() / (phi * phi).sum()
+    assert got_u == pytest.approx(amp_u, rel=1e-10)
+    assert got_v == pytest.approx(amp_v, rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Misfit (eq. (logl))
+
+def test_misfit_closed_forms():
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(100)
+    assert oracle.misfit(u, u, 0.3) == 0.0
+    assert oracle.misfit(u + 0.2, u, 0.5) == pytest.approx(100 * 0.04 / (2 * 0.25), rel=1e-14)
+    # equals -log of the Gaussian density up to its normalising constant
+    y = u + rng.standard_normal(100) * 0.1
+    from scipy import stats
+    logpdf = stats.norm(loc=u, scale=0.1).logpdf(y).sum()
+    const = -100 * math.log(0.1 * math.sqrt(2 * math.pi))
+    assert oracle.misfit(y, u, 0.1) == pytest.approx(const - logpdf, rel=1e-12)
+
+
+def test_loglik_batch_agrees_with_single_solves_and_flags_failure():
+    n = 8
+    theta_ok = (0.1, 0.9, 200.0, 10.0)
+    u0, v0 = oracle_ic(n, theta_ok)
+    y = np.ones((n, n))
+    th = np.array([theta_ok, (0.2, 0.5, 100.0, 20.0), (0.1, 0.9, 1e6, 10.0)])
+    phi, st, it = oracle.loglik_batch(th, u0, v0, y, 0.05, 2.5e-4, 20, rtol=1e-12)
+    for c in range(2):
+        u, v, _, s = oracle.forward_solve(th[c], u0, v0, 2.5e-4, 20, rtol=1e-12)
+        assert s == 0 and st[c] == 0
+        assert phi[c] == oracle.misfit(y, u, 0.05)
+    # gamma tau u v > 1 + gamma tau ... -> sigma_u < 0: the robust Phi is +inf
+    assert st[2] != 0 and phi[2] == math.inf
+
+
+def oracle_ic(n, theta, rel=0.01, seed=11):
+    a, b = theta[:2]
+    rng = np.random.default_rng(seed)
+    us, vs = a + b, b / (a + b) ** 2
+    return us * (1 + rel * rng.uniform(-1, 1, (n, n))), vs * (1 + rel * rng.uniform(-1, 1, (n, n)))
+
+
+# --------------------------------------------------------------------------
+# Sampler (Algorithm 1) on targets with known answers
+
+LO = np.array([-10.0, -10.0, 0.0, 0.0])
+HI = np.array([10.0, 10.0, 1.0, 1.0])
+
+
+def test_rwm_recovers_gaussian_toy_target():
+    mu = np.array([0.5, -1.0])
+    cov = np.array([[1.0, 0.6], [0.6, 2.0]])
+    icov = np.linalg.inv(cov)
+
+    def phi_fn(p):
+        e = np.atleast_2d(p)[:, :2] - mu
+        return 0.5 * np.einsum("ni,ij,nj->n", e, icov, e)
+
+    C, S = 400, 250
+    step = np.array([1.5, 1.5, 0.0, 0.0])
+    phis = np.tile(np.array([0.0, 0.0, 0.5, 0.5]), (C, 1))
+    ll = phi_fn(phis)
+    for s in range(S):
+        phis, ll, acc, _ = osamp.rwm_batch_step(phis, ll, 123, s, LO, HI, step, 0b0011, phi_fn)
+    x = phis[:, :2]
+    se = np.sqrt(np.diag(cov) / C)
+    assert np.all(np.abs(x.mean(0) - mu) < 4.5 * se)
+    emp = np.cov(x.T)
+    assert np.all(np.abs(emp - cov) < 4.5 * np.sqrt((cov ** 2 + np.outer(np.diag(cov), np.diag(cov))) / C))
+    assert np.allclose(ll, phi_fn(phis))
+    assert np.all(phis[:, 2:] == 0.5)  # fixed coordinates never move
+
+
+def test_rwm_flat_target_gives_prior_marginals():
+    from scipy import stats
+    C, S = 300, 120
+    lo = np.array([0.0, 2.0, 0.0, 0.0])
+    hi = np.array([1.0, 5.0, 1.0, 1.0])
+    step = 0.3 * (hi - lo)
+    phis = np.tile((lo + hi) / 2, (C, 1))
+    ll = np.zeros(C)
+    for s in range(S):
+        phis, ll, acc, inside = osamp.rwm_batch_step(phis, ll, 9, s, lo, hi, step, 0b1111,
+                                                      lambda p: np.zeros(len(p)))
+    for i in range(4):
+        z = (phis[:, i] - lo[i]) / (hi[i] - lo[i])
+        assert stats.kstest(z, "uniform").pvalue > 1e-3
+
+
+def test_da_with_exact_surrogate_never_rejects_at_stage_two_and_constant_is_plain():
+    mu = np.array([0.2, 0.1])
+
+    def phi_fn(p):
+        return 0.5 * float(((np.asarray(p)[:2] - mu) ** 2).sum() / 0.3 ** 2)
+
+    step = np.array([0.4, 0.4, 0.0, 0.0])
+    p0 = np.array([0.0, 0.0, 0.5, 0.5])
+    # exact surrogate: stage 2 always accepts what stage 1 accepted
+    p, ll, ls = p0.copy(), phi_fn(p0), phi_fn(p0)
+    for s in range(300):
+        p, ll, ls, a1, a, solved = osamp.da_step(p, ll, ls, 5, 0, s, LO, HI, step, 3, phi_fn, phi_fn)
+        if a1:
+            assert a
+    # constant surrogate: stage 1 always accepts and the path equals plain MH
+    pa, lla = p0.copy(), phi_fn(p0)
+    pb, llb, lsb = p0.copy(), phi_fn(p0), 0.0
+    for s in range(300):
+        pa, lla, _, _ = osamp.rwm_step(pa, lla, 5, 0, s, LO, HI, step, 3, phi_fn)
+        pb, llb, lsb, a1, _, _ = osamp.da_step(pb, llb, lsb, 5, 0, s, LO, HI, step, 3, phi_fn,
+                                               lambda q: 0.0)
+        assert a1
+        assert np.array_equal(pa, pb) and lla == llb
