@@ -1,0 +1,260 @@
+/*
+ * rdbayes — batched Bayesian parameter identification for the Schnakenberg
+ * (activator-depleted) reaction-diffusion system on MI355X (gfx950).
+ *
+ * Method: Campillo-Funollet, Venkataraman, Madzvamuse, "A Bayesian approach
+ * to parameter identification with an application to Turing systems"
+ * (arXiv:1605.04718).
+ *
+ * The library evaluates, for thousands of parameter vectors at once, the
+ * observation operator G (Sec. 2: parameters -> model solution at the
+ * measured time), the log-likelihood Phi = -log rho(y - G(p)) of eq. (logl)
+ * for Gaussian noise, and Metropolis-Hastings steps (Sec. 2, Algorithm 1)
+ * of independent chains, all in HIP kernels on one GPU.
+ *
+ * The forward model is eq. (schnakenberg) with the kinetics of
+ * eq. (reactions), on the unit square mapped from a uniformly growing domain
+ * rho(t) = exp(r t) (r = 0: stationary), discretised as in Sec. 3.1.1: a
+ * cell-centred n x n grid (h = 1/n) with the 5-point Laplacian and mirror
+ * (zero-flux) ghosts, and the IMEX backward-Euler step with one Picard
+ * linearisation
+ *   [1/dt + 2 r + g (1 - u^n v^n)] u^{n+1} - rho_n^-2 Lap_h u^{n+1} = u^n/dt + g a
+ *   [1/dt + 2 r + g (u^n)^2]       v^{n+1} - d rho_n^-2 Lap_h v^{n+1} = v^n/dt + g b
+ * (g = gamma; both systems solved by unpreconditioned conjugate gradients,
+ * stopping when ||r||_2 <= cg_rtol ||rhs||_2 on the recursive residual).
+ *
+ * Conventions for every entry point:
+ *  - Return value: RD_OK (0) or a negative call error (RD_E*).  A call
+ *    error is reported synchronously before any work is enqueued; the text
+ *    is available from rd_last_error() (thread-local).
+ *  - Numerical failures are not call errors: they are reported per item in
+ *    `status` as RD_ST_* bit flags, and a failed solve has Phi = +inf, so a
+ *    proposal that needs it is rejected (the "robust" likelihood of Sec. 2).
+ *  - "dev" arrays are device pointers on the current HIP device, owned by
+ *    the caller, and must stay valid until the stream has finished the call.
+ *    "host" arrays are read during the call only.
+ *  - Batch calls only enqueue work on `stream` (a hipStream_t, NULL = the
+ *    null stream) and never synchronise; results are valid once the caller
+ *    has synchronised that stream.  A problem handle may be used from one
+ *    stream at a time (its workspace is shared by its calls).
+ *  - Parameter vectors are float64 [n][4]: natural theta = (a, b, gamma, d),
+ *    sampling coordinates phi = (a, b, ln gamma, ln d).
+ *  - Fields are row-major [n_cells_y][n_cells_x] with x fastest.
+ */
+#ifndef RDBAYES_H
+#define RDBAYES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RD_OK = 0,
+    RD_EINVAL = -1,       /* bad argument, shape or size */
+    RD_EHIP = -2,         /* a HIP runtime call failed */
+    RD_ENOMEM = -3,       /* device allocation failed */
+    RD_EUNSUPPORTED = -4  /* valid request this build does not implement */
+};
+
+/* Per-item status bits. */
+enum {
+    RD_ST_NOT_CONVERGED = 1, /* CG reached cg_maxit */
+    RD_ST_BREAKDOWN = 2,     /* p.Ap <= 0: the implicit operator lost definiteness */
+    RD_ST_NONFINITE = 4,     /* NaN/Inf in a field or reduction */
+    RD_ST_OUT_OF_PRIOR = 8   /* proposal outside the prior box: not solved */
+};
+
+enum { RD_PRECISION_FP32 = 0, RD_PRECISION_FP64 = 1 };
+enum { RD_MODE_PLAIN = 0, RD_MODE_DA = 1 };
+enum { RD_MAX_GRIDS = 8 };
+
+typedef struct rd_problem rd_problem; /* opaque; owned by the library */
+
+/* One grid class: a grid size, a growth law and its data set. */
+typedef struct {
+    int32_t n;            /* cells per side; 32, 64, 128 or 256 */
+    int32_t growth;       /* 0: rho = 1; 1: rho(t) = exp(growth_rate t) */
+    double growth_rate;   /* r of rho = exp(r t); dilution term 2 r (m = 2) */
+    const double *u0;     /* host [n*n] initial u (fixed for every proposal) */
+    const double *v0;     /* host [n*n] initial v */
+    const double *y;      /* host [n*n] observed u at T = dt * n_steps, or NULL
+                             (then likelihood calls on this class fail RD_EINVAL) */
+    double sigma;         /* standard deviation of the Gaussian noise of y */
+} rd_grid_desc;
+
+/* Problem description (copied by init_problem). */
+typedef struct {
+    int32_t n_grids;               /* 1 .. RD_MAX_GRIDS */
+    const rd_grid_desc *grids;     /* host [n_grids] */
+    double dt;                     /* time step tau */
+    int32_t n_steps;               /* T = dt * n_steps */
+    double cg_rtol;                /* CG stop: ||r|| <= cg_rtol ||rhs|| */
+    int32_t cg_maxit;              /* CG iteration cap per solve (<= 0: 10 n^2) */
+    int32_t precision;             /* RD_PRECISION_FP32: fields and CG vectors in
+                                      FP32, dot products, CG scalars and Phi in
+                                      FP64.  RD_PRECISION_FP64: everything FP64 */
+    uint32_t free_mask;            /* bit i set: sampling coordinate i moves */
+    double lo[4], hi[4];           /* uniform prior box in sampling coordinates */
+    double step[4];                /* random-walk proposal s.d. per coordinate */
+    int32_t max_batch;             /* largest n / n_chains any call will pass */
+} rd_problem_desc;
+
+/* Creates a problem: validates the description, uploads the initial fields
+ * and data, sizes the workspace for max_batch items and picks the solver
+ * tile shape for each grid class (autotuned once per device and grid class,
+ * see rd_autotune).  Synchronous.  Errors: RD_EINVAL, RD_EHIP, RD_ENOMEM,
+ * RD_EUNSUPPORTED (grid size without a kernel, FP64 at n = 256 resident). */
+int32_t init_problem(const rd_problem_desc *desc, rd_problem **out);
+
+/* Releases the workspace (synchronises the device first).  NULL is a no-op. */
+int32_t destroy_problem(rd_problem *p);
+
+/* G(theta) for n parameter vectors (Sec. 2 observation operator): integrate
+ * each from the initial fields of its grid class to T.
+ *   theta    dev float64 [n][4] natural parameters (a, b, gamma, d)
+ *   grid_id  dev int32 [n] grid class of each item, or NULL (class 0)
+ *   u_out    dev [n][N*N] final u (float32 for FP32 problems, float64 for
+ *            FP64 problems), or NULL; only allowed when every item has the
+ *            same grid size N (pass N = the size of grid 0)
+ *   v_out    same layout for v, or NULL
+ *   status   dev int32 [n] RD_ST_* bits (0 = success), required
+ *   cg_iters dev int32 [n][2] total CG iterations of the u and v systems,
+ *            or NULL
+ * Errors: RD_EINVAL (n < 0 or n > max_batch, NULL status, mixed sizes with
+ * field outputs). */
+int32_t forward_solve_batch(rd_problem *p, int32_t n, const double *theta,
+                            const int32_t *grid_id, void *u_out, void *v_out,
+                            int32_t *status, int32_t *cg_iters, void *stream);
+
+/* Phi(theta; y) = |y - G(theta)|^2 / (2 sigma^2) for each item, eq. (logl)
+ * with Gaussian noise (the additive constant is dropped; only differences
+ * enter Algorithm 1).  The solve and the misfit run fused in one kernel; the
+ * misfit is accumulated in float64.  A failed solve gives phi = +inf.
+ *   phi dev float64 [n]; status dev int32 [n]; cg_iters dev int32 [n][2] or NULL */
+int32_t log_likelihood_batch(rd_problem *p, int32_t n, const double *theta,
+                             const int32_t *grid_id, double *phi, int32_t *status,
+                             int32_t *cg_iters, void *stream);
+
+/* Misfit of caller-supplied u fields against the data of their grid class
+ * (the misfit kernel alone).  u dev [n][N*N] in the problem's precision. */
+int32_t field_misfit_batch(rd_problem *p, int32_t n, const void *u, const int32_t *grid_id,
+                           double *phi, void *stream);
+
+/* State of a batch of independent Metropolis chains; all arrays are
+ * caller-owned device arrays with n_chains rows. */
+typedef struct {
+    int32_t n_chains;
+    double *phi;           /* dev [n][4] current state, sampling coordinates */
+    double *loglik;        /* dev [n] Phi at the current state (+inf allowed) */
+    double *loglik_sur;    /* dev [n] surrogate Phi~ at the current state
+                              (RD_MODE_DA only, else may be NULL) */
+    const int32_t *grid_id;/* dev [n] grid class per chain, or NULL (class 0) */
+    uint64_t *n_accept;    /* dev [n] accepted proposals */
+    uint64_t *n_accept1;   /* dev [n] first-stage accepts (DA), or NULL */
+    uint64_t *n_solves;    /* dev [n] forward solves performed */
+    double *trace;         /* dev [n_steps][n][4] states after each step, or NULL */
+    uint32_t seed;         /* Philox key word 1 (key word 0 = chain index) */
+    uint64_t step;         /* index of the next step; advanced by the calls */
+} rd_chains;
+
+/* n_steps Metropolis-Hastings steps (Sec. 2, Algorithm 1) of every chain.
+ * Proposal: phi' = phi + step .* z on the free coordinates, z ~ N(0, I) by
+ * Box-Muller from Philox4x32-10 (key = (chain, seed), counter = (step lo,
+ * step hi, purpose 0, block)).  A proposal outside the prior box is rejected
+ * without a solve (status RD_ST_OUT_OF_PRIOR is not reported: it is a
+ * rejection).  Otherwise Phi(phi') is computed by the fused solve + misfit
+ * and the proposal is accepted iff log U < Phi(phi) - Phi(phi'), U in (0,1)
+ * from purpose 1.
+ * mode RD_MODE_DA: delayed acceptance (Christen and Fox 2005): first stage
+ * on the surrogate (requires surrogate_create + surrogate data), uniform from
+ * purpose 2; only first-stage accepts are solved; the second stage accepts
+ * iff log U < [Phi(phi) - Phi(phi')] - [Phi~(phi) - Phi~(phi')].
+ * On a created stream the steps are replayed from one captured HIP graph per
+ * chains layout; on the null stream they are launched directly.
+ * chains->step is advanced by n_steps on return (host field).  The trace, if
+ * given, must have room for n_steps rows.
+ * Errors: RD_EINVAL (shapes, NULL required arrays), RD_EUNSUPPORTED (DA
+ * without a surrogate). */
+int32_t mcmc_step_batch(rd_problem *p, rd_chains *chains, int32_t n_steps, int32_t mode,
+                        void *stream);
+
+/* The two halves of one plain step, for samplers on an external Phi (the
+ * non-intrusive use of Sec. 2, and toy targets in tests):
+ * propose_batch writes phi_prop dev float64 [n][4] and inside dev int32 [n]
+ * (1 = in the prior box) for step chains->step; accept_batch then takes
+ * Phi(phi_prop) from the caller (dev float64 [n], ignored where inside = 0),
+ * applies the accept test of that same step, updates the chains and
+ * advances chains->step by one. */
+int32_t propose_batch(rd_problem *p, rd_chains *chains, double *phi_prop, int32_t *inside,
+                      void *stream);
+int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *phi_prop,
+                     const int32_t *inside, const double *loglik_prop, void *stream);
+
+/* ---- surrogate (first stage of delayed acceptance) ----------------------
+ * An MLP 4 -> width x depth (GELU) -> (n/ds)^2 maps the sampling coordinates
+ * (scaled to [-1, 1] on the prior box) to the block-mean-downsampled u field
+ * (per-pixel standardised).  Trained and evaluated by BF16 MFMA kernels with
+ * FP32 accumulation and FP32 master weights. */
+
+/* Creates (or re-creates) the surrogate of grid class 0 with PyTorch-default
+ * uniform(+-1/sqrt(fan_in)) initialisation from `seed`; out_side = the side of
+ * the downsampled field (32); width 512, depth 4 in the reference setup.
+ * Errors: RD_EINVAL (sizes), RD_ENOMEM. */
+int32_t surrogate_create(rd_problem *p, int32_t width, int32_t depth, int32_t out_side,
+                         uint32_t seed);
+
+/* Block means of u fields: dev [n][N*N] (problem precision) -> dev float32
+ * [n][out_side^2] (non-overlapping (N/out_side)^2 blocks). */
+int32_t downsample_batch(rd_problem *p, int32_t n, const void *u, float *out, void *stream);
+
+/* Sets the per-pixel standardisation (dev float32 [out^2] mean and sd) and the
+ * first-stage data: ybar = block means of y (computed by the library), and the
+ * first-stage noise s.d. sigma1 (per pixel). */
+int32_t surrogate_set_scaling(rd_problem *p, const float *mean, const float *sd,
+                              double sigma1, void *stream);
+
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on a batch:
+ *   phi dev float64 [batch][4] sampling coordinates
+ *   target dev float32 [batch][out^2] standardised downsampled fields
+ *   loss_out dev float64 [1] mean squared error of the batch (before the
+ *   step), or NULL.  batch <= 4096. */
+int32_t surrogate_train_step(rd_problem *p, int32_t batch, const double *phi, const float *target,
+                             double lr, double *loss_out, void *stream);
+
+/* Surrogate prediction: dev float64 [n][4] -> dev float32 [n][out^2]
+ * (standardised space if raw = 1, else de-standardised u block means). */
+int32_t surrogate_forward(rd_problem *p, int32_t n, const double *phi, float *out, int32_t raw,
+                          void *stream);
+
+/* Surrogate misfit Phi~ = |ybar - u~|^2 / (2 sigma1^2) per item: dev [n]. */
+int32_t surrogate_loglik_batch(rd_problem *p, int32_t n, const double *phi, double *phi_sur,
+                               void *stream);
+
+/* Copies FP32 master weights / biases of layer `layer` to caller memory
+ * (dev float32, [out][in] row-major and [out]) or from it (dir = 1). */
+int32_t surrogate_params(rd_problem *p, int32_t layer, float *w, float *b, int32_t dir,
+                         void *stream);
+
+/* ---- utilities ----------------------------------------------------------- */
+
+/* Re-runs the tile-shape autotuner for every grid class of p (a few timed
+ * trial solves) and keeps the fastest; returns the chosen cells-per-thread
+ * of each class in cpt_out (host int32 [n_grids], may be NULL). */
+int32_t rd_autotune(rd_problem *p, int32_t *cpt_out);
+
+/* Accumulated device time (ms, measured with HIP events on the launch
+ * stream) and launch count of the fused solve kernel since the last reset;
+ * reset = 1 clears after reading.  Timing is recorded only while enabled. */
+int32_t rd_solver_timing(rd_problem *p, int32_t enable, double *ms_total, int64_t *launches,
+                         int32_t reset);
+
+const char *rd_status_string(int32_t status_or_error);
+const char *rd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RDBAYES_H */

@@ -1,0 +1,227 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Device arrays are torch tensors on the current HIP device; the library
+enqueues its kernels on torch's current stream.  Nothing here computes a
+step of the method.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Chains, GridDesc, ProblemDesc, check, lib
+
+PLAIN, DA = _lib.MODE_PLAIN, _lib.MODE_DA
+FP32, FP64 = _lib.PRECISION_FP32, _lib.PRECISION_FP64
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device arrays must be HIP tensors")
+    if not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Grid:
+    """One grid class: size n, growth law, initial fields and data (host float64)."""
+    n: int
+    u0: np.ndarray
+    v0: np.ndarray
+    y: np.ndarray | None = None
+    sigma: float = 1.0
+    growth: int = 0
+    growth_rate: float = 0.0
+
+
+class Problem:
+    """Owns an rd_problem handle (init_problem / destroy_problem)."""
+
+    def __init__(self, grids, dt, n_steps, cg_rtol, *, precision=FP32, cg_maxit=0,
+                 free_mask=0b1111, lo=(0, 0, 0, 0), hi=(1, 1, 1, 1), step=(0, 0, 0, 0),
+                 max_batch=4096):
+        if isinstance(grids, Grid):
+            grids = [grids]
+        self.grids = list(grids)
+        self.precision = precision
+        self.max_batch = max_batch
+        self.n_steps = n_steps
+        self.dt = dt
+        keep = []
+        gd = (GridDesc * len(self.grids))()
+        for k, g in enumerate(self.grids):
+            u0 = np.ascontiguousarray(g.u0, dtype=np.float64).reshape(-1)
+            v0 = np.ascontiguousarray(g.v0, dtype=np.float64).reshape(-1)
+            if u0.size != g.n * g.n or v0.size != g.n * g.n:
+                raise ValueError("u0/v0 must have n*n entries")
+            keep += [u0, v0]
+            gd[k].n = g.n
+            gd[k].growth = g.growth
+            gd[k].growth_rate = g.growth_rate
+            gd[k].u0 = u0.ctypes.data_as(_lib.c_dp)
+            gd[k].v0 = v0.ctypes.data_as(_lib.c_dp)
+            if g.y is not None:
+                y = np.ascontiguousarray(g.y, dtype=np.float64).reshape(-1)
+                if y.size != g.n * g.n:
+                    raise ValueError("y must have n*n entries")
+                keep.append(y)
+                gd[k].y = y.ctypes.data_as(_lib.c_dp)
+            gd[k].sigma = g.sigma
+        d = ProblemDesc()
+        d.n_grids = len(self.grids)
+        d.grids = gd
+        d.dt = dt
+        d.n_steps = n_steps
+        d.cg_rtol = cg_rtol
+        d.cg_maxit = cg_maxit
+        d.precision = precision
+        d.free_mask = free_mask
+        for i in range(4):
+            d.lo[i], d.hi[i], d.step[i] = lo[i], hi[i], step[i]
+        d.max_batch = max_batch
+        h = ctypes.c_void_p()
+        torch.cuda.init()
+        check(lib().init_problem(ctypes.byref(d), ctypes.byref(h)), "init_problem")
+        self.h = h
+        del keep
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().destroy_problem(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def field_dtype(self):
+        return torch.float32 if self.precision == FP32 else torch.float64
+
+    # -- forward map and likelihood -------------------------------------
+    def forward_solve(self, theta, grid_id=None, fields=True, stream=None):
+        """theta: HIP float64 [n, 4] (a, b, gamma, d).  Returns (u, v, status, iters)."""
+        n = theta.shape[0]
+        N = self.grids[0].n
+        dev = theta.device
+        u = torch.empty((n, N, N), dtype=self.field_dtype, device=dev) if fields else None
+        v = torch.empty((n, N, N), dtype=self.field_dtype, device=dev) if fields else None
+        st = torch.empty(n, dtype=torch.int32, device=dev)
+        it = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        check(lib().forward_solve_batch(self.h, n, _ptr(theta), _ptr(grid_id), _ptr(u), _ptr(v),
+                                        _ptr(st), _ptr(it), _stream(stream)), "forward_solve_batch")
+        return u, v, st, it
+
+    def log_likelihood(self, theta, grid_id=None, stream=None):
+        """Returns (phi float64 [n], status int32 [n], iters int32 [n, 2])."""
+        n = theta.shape[0]
+        dev = theta.device
+        phi = torch.empty(n, dtype=torch.float64, device=dev)
+        st = torch.empty(n, dtype=torch.int32, device=dev)
+        it = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        check(lib().log_likelihood_batch(self.h, n, _ptr(theta), _ptr(grid_id), _ptr(phi),
+                                         _ptr(st), _ptr(it), _stream(stream)),
+              "log_likelihood_batch")
+        return phi, st, it
+
+    def field_misfit(self, u, stream=None):
+        n = u.shape[0]
+        phi = torch.empty(n, dtype=torch.float64, device=u.device)
+        check(lib().field_misfit_batch(self.h, n, _ptr(u), None, _ptr(phi), _stream(stream)),
+              "field_misfit_batch")
+        return phi
+
+    # -- sampler ----------------------------------------------------------
+    def mcmc_step(self, chains: "ChainState", n_steps=1, mode=PLAIN, stream=None):
+        c = chains.struct()
+        check(lib().mcmc_step_batch(self.h, ctypes.byref(c), n_steps, mode, _stream(stream)),
+              "mcmc_step_batch")
+        chains.step = int(c.step)
+
+    def propose(self, chains: "ChainState", stream=None):
+        n = chains.n
+        dev = chains.phi.device
+        prop = torch.empty((n, 4), dtype=torch.float64, device=dev)
+        inside = torch.empty(n, dtype=torch.int32, device=dev)
+        c = chains.struct()
+        check(lib().propose_batch(self.h, ctypes.byref(c), _ptr(prop), _ptr(inside),
+                                  _stream(stream)), "propose_batch")
+        return prop, inside
+
+    def accept(self, chains: "ChainState", prop, inside, loglik_prop, stream=None):
+        c = chains.struct()
+        check(lib().accept_batch(self.h, ctypes.byref(c), _ptr(prop), _ptr(inside),
+                                 _ptr(loglik_prop), _stream(stream)), "accept_batch")
+        chains.step = int(c.step)
+
+    # -- utilities --------------------------------------------------------
+    def autotune(self):
+        out = (ctypes.c_int32 * len(self.grids))()
+        check(lib().rd_autotune(self.h, ctypes.cast(out, ctypes.c_void_p)), "rd_autotune")
+        return list(out)
+
+    def solver_timing(self, enable=True, reset=False):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(lib().rd_solver_timing(self.h, int(enable), ctypes.byref(ms), ctypes.byref(n),
+                                     int(reset)), "rd_solver_timing")
+        return ms.value, n.value
+
+
+@dataclass
+class ChainState:
+    """Device state of a batch of chains (the rd_chains struct's arrays)."""
+    phi: torch.Tensor
+    loglik: torch.Tensor
+    seed: int = 4
+    step: int = 0
+    loglik_sur: torch.Tensor | None = None
+    grid_id: torch.Tensor | None = None
+    n_accept: torch.Tensor | None = None
+    n_accept1: torch.Tensor | None = None
+    n_solves: torch.Tensor | None = None
+    trace: torch.Tensor | None = None
+
+    @property
+    def n(self):
+        return self.phi.shape[0]
+
+    @classmethod
+    def create(cls, phi, loglik, seed=4, step=0, trace_steps=0, da=False, grid_id=None):
+        dev = phi.device
+        n = phi.shape[0]
+        z = lambda: torch.zeros(n, dtype=torch.int64, device=dev)  # noqa: E731
+        return cls(phi=phi.contiguous(), loglik=loglik.contiguous(), seed=seed, step=step,
+                   loglik_sur=torch.zeros(n, dtype=torch.float64, device=dev) if da else None,
+                   grid_id=grid_id, n_accept=z(), n_accept1=z(), n_solves=z(),
+                   trace=(torch.zeros((trace_steps, n, 4), dtype=torch.float64, device=dev)
+                          if trace_steps else None))
+
+    def struct(self) -> Chains:
+        c = Chains()
+        c.n_chains = self.n
+        c.phi = _ptr(self.phi)
+        c.loglik = _ptr(self.loglik)
+        c.loglik_sur = _ptr(self.loglik_sur)
+        c.grid_id = _ptr(self.grid_id)
+        c.n_accept = _ptr(self.n_accept)
+        c.n_accept1 = _ptr(self.n_accept1)
+        c.n_solves = _ptr(self.n_solves)
+        c.trace = _ptr(self.trace)
+        c.seed = self.seed
+        c.step = self.step
+        return c

@@ -1,0 +1,866 @@
+// C ABI of the library: problem handle, workspace, launch sequencing.
+// Every entry point validates its arguments on the host, enqueues kernels
+// on the caller's stream and returns; nothing here computes a step of the
+// method on the host.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/rdbayes.h"
+#include "rd_internal.hpp"
+#include "rd_mlp.hpp"
+#include "rd_sampler.hpp"
+
+using namespace rd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int32_t fail(int32_t code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(RD_EHIP, "%s: %s", #expr, hipGetErrorString(e_));              \
+    } while (0)
+
+// Autotuned tile per (device, n, precision), shared by every problem of the
+// process.
+std::mutex g_tune_mu;
+std::map<long, int> g_tuned;
+
+long tune_key(int dev, int n, int prec)
+{
+    return ((long)dev << 32) | ((long)n << 2) | prec;
+}
+
+}  // namespace
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    // identity of what was captured
+    rd_chains key{};
+    int mode = 0;
+    hipStream_t stream = nullptr;
+};
+
+struct rd_problem {
+    int device = 0;
+    int n_cu = 0;
+    rd_problem_desc desc{};
+    std::vector<rd_grid_desc> grid_desc;
+    std::vector<GridDev> grids_host;
+    GridDev *grids_dev = nullptr;
+    std::vector<void *> allocs;
+    TileChoice tile[RD_MAX_GRIDS]{};
+    int wgs_per_cu[RD_MAX_GRIDS]{};  // resident workgroups per CU of tile[g]
+    int maxit = 0;
+    // workspace [max_batch]
+    unsigned *queue = nullptr;
+    double *theta_prop = nullptr;
+    double *phi_prop = nullptr;
+    int *inside = nullptr;
+    int *need = nullptr;
+    double *ll_prop = nullptr;
+    double *ll_sur_prop = nullptr;
+    int *status_ws = nullptr;
+    uint64_t *ctr = nullptr;
+    void *gws = nullptr;
+    int gws_slots = 0;
+    // timing of the fused solve kernel
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<hipEvent_t> free_events;
+    double ms_total = 0.0;
+    int64_t launches = 0;
+    // captured MCMC steps
+    std::vector<GraphEntry> graphs;
+    bool use_graphs = true;
+    // surrogate
+    Surrogate *sur = nullptr;
+};
+
+namespace {
+
+void *dmalloc(rd_problem *p, size_t bytes, int32_t *err)
+{
+    void *ptr = nullptr;
+    if (bytes == 0)
+        bytes = 16;
+    if (hipMalloc(&ptr, bytes) != hipSuccess) {
+        *err = fail(RD_ENOMEM, "hipMalloc(%zu) failed", bytes);
+        return nullptr;
+    }
+    p->allocs.push_back(ptr);
+    return ptr;
+}
+
+int32_t upload_field(rd_problem *p, const double *host, int nn, void **out)
+{
+    int32_t err = RD_OK;
+    if (p->desc.precision == RD_PRECISION_FP32) {
+        std::vector<float> f(nn);
+        for (int k = 0; k < nn; ++k)
+            f[k] = (float)host[k];
+        *out = dmalloc(p, sizeof(float) * nn, &err);
+        if (!*out)
+            return err;
+        HIP_TRY(hipMemcpy(*out, f.data(), sizeof(float) * nn, hipMemcpyHostToDevice));
+    } else {
+        *out = dmalloc(p, sizeof(double) * nn, &err);
+        if (!*out)
+            return err;
+        HIP_TRY(hipMemcpy(*out, host, sizeof(double) * nn, hipMemcpyHostToDevice));
+    }
+    return RD_OK;
+}
+
+hipError_t record_solve_start(rd_problem *p, hipStream_t s, hipEvent_t *ev)
+{
+    *ev = nullptr;
+    if (!p->timing)
+        return hipSuccess;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipStreamIsCapturing(s, &cs);
+    if (cs != hipStreamCaptureStatusNone)
+        return hipSuccess;
+    hipEvent_t e;
+    if (!p->free_events.empty()) {
+        e = p->free_events.back();
+        p->free_events.pop_back();
+    } else {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess)
+            return r;
+    }
+    *ev = e;
+    return hipEventRecord(e, s);
+}
+
+hipError_t record_solve_end(rd_problem *p, hipStream_t s, hipEvent_t start)
+{
+    if (!start)
+        return hipSuccess;
+    hipEvent_t e;
+    if (!p->free_events.empty()) {
+        e = p->free_events.back();
+        p->free_events.pop_back();
+    } else {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess)
+            return r;
+    }
+    p->pending.push_back({start, e});
+    return hipEventRecord(e, s);
+}
+
+// Enqueue: reset the queue head, then the persistent fused solve.
+int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid_id,
+                      const int *need, double *phi, int *status, int *iters, void *u_out,
+                      void *v_out, hipStream_t s)
+{
+    if (n == 0)
+        return RD_OK;
+    if (p->desc.n_grids != 1 && grid_id)
+        return fail(RD_EUNSUPPORTED, "mixed grid classes are served by the mixed solve");
+    const int g = 0;
+    const int nn = p->grids_host[g].n;
+    SolveArgs a{};
+    a.grids = p->grids_dev;
+    a.n_items = n;
+    a.order = nullptr;
+    a.grid_id = grid_id;
+    a.theta = theta;
+    a.need = need;
+    a.dt = p->desc.dt;
+    a.n_steps = p->desc.n_steps;
+    a.rtol2 = p->desc.cg_rtol * p->desc.cg_rtol;
+    a.maxit = p->maxit;
+    a.phi = phi;
+    a.status = status;
+    a.iters = iters;
+    a.u_out = u_out;
+    a.v_out = v_out;
+    a.queue = p->queue;
+    a.gws = p->gws;
+    a.gws_slots = p->gws_slots;
+    const TileChoice t = p->tile[g];
+    // wgs_per_cu was queried when the tile was chosen: no runtime query may
+    // run here, since this is also called while a stream is being captured.
+    int wgs = p->n_cu * p->wgs_per_cu[g];
+    if (wgs > n)
+        wgs = n;
+    HIP_TRY(launch_fill_u32(p->queue, 0u, 1, s));
+    hipEvent_t e0;
+    HIP_TRY(record_solve_start(p, s, &e0));
+    HIP_TRY(launch_solve(nn, p->desc.precision, t, a, wgs, s));
+    HIP_TRY(record_solve_end(p, s, e0));
+    return RD_OK;
+}
+
+int32_t check_chains(rd_problem *p, const rd_chains *c, int mode)
+{
+    if (!c)
+        return fail(RD_EINVAL, "chains is NULL");
+    if (c->n_chains < 0 || c->n_chains > p->desc.max_batch)
+        return fail(RD_EINVAL, "n_chains %d outside [0, max_batch=%d]", c->n_chains,
+                    p->desc.max_batch);
+    if (!c->phi || !c->loglik)
+        return fail(RD_EINVAL, "chains->phi and chains->loglik are required");
+    if (mode == RD_MODE_DA && !c->loglik_sur)
+        return fail(RD_EINVAL, "delayed acceptance needs chains->loglik_sur");
+    return RD_OK;
+}
+
+SamplerArgs sampler_args(rd_problem *p, const rd_chains *c)
+{
+    SamplerArgs a{};
+    a.n = c->n_chains;
+    a.seed = c->seed;
+    a.ctr = p->ctr;
+    a.cfg.free_mask = p->desc.free_mask;
+    for (int i = 0; i < 4; ++i) {
+        a.cfg.lo[i] = p->desc.lo[i];
+        a.cfg.hi[i] = p->desc.hi[i];
+        a.cfg.step[i] = p->desc.step[i];
+    }
+    a.phi = c->phi;
+    a.loglik = c->loglik;
+    a.loglik_sur = c->loglik_sur;
+    a.phi_prop = p->phi_prop;
+    a.theta_prop = p->theta_prop;
+    a.inside = p->inside;
+    a.need = p->need;
+    a.loglik_prop = p->ll_prop;
+    a.loglik_sur_prop = p->ll_sur_prop;
+    a.n_accept = c->n_accept;
+    a.n_accept1 = c->n_accept1;
+    a.n_solves = c->n_solves;
+    a.trace = c->trace;
+    return a;
+}
+
+// One MCMC step as a kernel sequence (the unit that is captured in a graph).
+int32_t enqueue_mcmc_step(rd_problem *p, const rd_chains *c, int mode, hipStream_t s)
+{
+    SamplerArgs a = sampler_args(p, c);
+    HIP_TRY(launch_propose(a, s));
+    if (mode == RD_MODE_PLAIN) {
+        HIP_TRY(launch_copy_i32(p->inside, p->need, c->n_chains, s));
+    } else {
+        int32_t r = surrogate_enqueue_loglik(p->sur, c->n_chains, p->phi_prop, p->ll_sur_prop, s);
+        if (r != RD_OK)
+            return fail(r, "surrogate evaluation failed: %s", hipGetErrorString(hipGetLastError()));
+        HIP_TRY(launch_da_stage1(a, s));
+    }
+    int32_t r = enqueue_solve(p, c->n_chains, p->theta_prop, c->grid_id, p->need, p->ll_prop,
+                              p->status_ws, nullptr, nullptr, nullptr, s);
+    if (r != RD_OK)
+        return r;
+    if (mode == RD_MODE_PLAIN)
+        HIP_TRY(launch_accept(a, s));
+    else
+        HIP_TRY(launch_da_stage2(a, s));
+    HIP_TRY(launch_advance_ctr(p->ctr, s));
+    return RD_OK;
+}
+
+bool same_chains(const rd_chains &a, const rd_chains &b)
+{
+    return a.n_chains == b.n_chains && a.phi == b.phi && a.loglik == b.loglik &&
+           a.loglik_sur == b.loglik_sur && a.grid_id == b.grid_id && a.n_accept == b.n_accept &&
+           a.n_accept1 == b.n_accept1 && a.n_solves == b.n_solves && a.trace == b.trace &&
+           a.seed == b.seed;
+}
+
+void drop_graphs(rd_problem *p)
+{
+    for (auto &g : p->graphs) {
+        if (g.exec)
+            hipGraphExecDestroy(g.exec);
+        if (g.graph)
+            hipGraphDestroy(g.graph);
+    }
+    p->graphs.clear();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
+{
+    if (!desc || !out)
+        return fail(RD_EINVAL, "desc and out are required");
+    *out = nullptr;
+    if (desc->n_grids < 1 || desc->n_grids > RD_MAX_GRIDS || !desc->grids)
+        return fail(RD_EINVAL, "n_grids must be in [1, %d]", RD_MAX_GRIDS);
+    if (!(desc->dt > 0.0) || desc->n_steps < 0)
+        return fail(RD_EINVAL, "dt must be > 0 and n_steps >= 0");
+    if (!(desc->cg_rtol > 0.0))
+        return fail(RD_EINVAL, "cg_rtol must be > 0");
+    if (desc->precision != RD_PRECISION_FP32 && desc->precision != RD_PRECISION_FP64)
+        return fail(RD_EINVAL, "precision must be 0 (FP32) or 1 (FP64)");
+    if (desc->max_batch < 1)
+        return fail(RD_EINVAL, "max_batch must be >= 1");
+    for (int i = 0; i < 4; ++i)
+        if (!(desc->lo[i] <= desc->hi[i]) || !(desc->step[i] >= 0.0))
+            return fail(RD_EINVAL, "prior box / step of coordinate %d invalid", i);
+    for (int g = 0; g < desc->n_grids; ++g) {
+        const rd_grid_desc &gd = desc->grids[g];
+        if (!tile_supported(gd.n, desc->precision, default_cpt(gd.n, desc->precision)))
+            return fail(RD_EUNSUPPORTED, "grid %d: n = %d has no kernel at this precision", g, gd.n);
+        if (!gd.u0 || !gd.v0)
+            return fail(RD_EINVAL, "grid %d: u0 and v0 are required", g);
+        if (gd.growth != 0 && gd.growth != 1)
+            return fail(RD_EINVAL, "grid %d: growth must be 0 or 1", g);
+        if (gd.y && !(gd.sigma > 0.0))
+            return fail(RD_EINVAL, "grid %d: sigma must be > 0", g);
+    }
+
+    rd_problem *p = new rd_problem();
+    p->desc = *desc;
+    p->grid_desc.assign(desc->grids, desc->grids + desc->n_grids);
+    p->desc.grids = p->grid_desc.data();
+    int32_t err = RD_OK;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&p->device) != hipSuccess ||
+        hipGetDeviceProperties(&prop, p->device) != hipSuccess) {
+        delete p;
+        return fail(RD_EHIP, "no HIP device");
+    }
+    p->n_cu = prop.multiProcessorCount;
+    int max_n = 0;
+    for (int g = 0; g < desc->n_grids; ++g) {
+        const rd_grid_desc &gd = desc->grids[g];
+        const int nn = gd.n * gd.n;
+        max_n = std::max(max_n, gd.n);
+        GridDev d{};
+        d.n = gd.n;
+        d.growth = gd.growth;
+        d.rate = gd.growth ? gd.growth_rate : 0.0;
+        if ((err = upload_field(p, gd.u0, nn, (void **)&d.u0)) != RD_OK ||
+            (err = upload_field(p, gd.v0, nn, (void **)&d.v0)) != RD_OK) {
+            destroy_problem(p);
+            return err;
+        }
+        if (gd.y) {
+            double *y = (double *)dmalloc(p, sizeof(double) * nn, &err);
+            if (!y || hipMemcpy(y, gd.y, sizeof(double) * nn, hipMemcpyHostToDevice) != hipSuccess) {
+                destroy_problem(p);
+                return err != RD_OK ? err : fail(RD_EHIP, "upload of y failed");
+            }
+            d.y = y;
+            d.inv_2s2 = 0.5 / (gd.sigma * gd.sigma);
+        }
+        d.cost = (double)nn;
+        p->grids_host.push_back(d);
+        int cpt = default_cpt(gd.n, desc->precision);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find(tune_key(p->device, gd.n, desc->precision));
+            if (it != g_tuned.end())
+                cpt = it->second;
+        }
+        p->tile[g] = TileChoice{cpt, nn / cpt};
+        p->wgs_per_cu[g] = solve_wgs_per_cu(gd.n, desc->precision, cpt);
+    }
+    p->maxit = desc->cg_maxit > 0 ? desc->cg_maxit : 10 * max_n * max_n;
+    const int B = desc->max_batch;
+    p->grids_dev = (GridDev *)dmalloc(p, sizeof(GridDev) * desc->n_grids, &err);
+    p->queue = (unsigned *)dmalloc(p, 64, &err);
+    p->ctr = (uint64_t *)dmalloc(p, 64, &err);
+    p->theta_prop = (double *)dmalloc(p, sizeof(double) * 4 * B, &err);
+    p->phi_prop = (double *)dmalloc(p, sizeof(double) * 4 * B, &err);
+    p->inside = (int *)dmalloc(p, sizeof(int) * B, &err);
+    p->need = (int *)dmalloc(p, sizeof(int) * B, &err);
+    p->ll_prop = (double *)dmalloc(p, sizeof(double) * B, &err);
+    p->ll_sur_prop = (double *)dmalloc(p, sizeof(double) * B, &err);
+    p->status_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
+    if (err != RD_OK) {
+        destroy_problem(p);
+        return err;
+    }
+    if (hipMemcpy(p->grids_dev, p->grids_host.data(), sizeof(GridDev) * desc->n_grids,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        launch_grid_coeffs(p->grids_dev, desc->n_grids, desc->dt, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        destroy_problem(p);
+        return fail(RD_EHIP, "upload of grid table failed");
+    }
+    // Streamed workspace: one slot per resident workgroup of the largest
+    // streamed class.
+    size_t slot = 0;
+    int slots = 0;
+    for (int g = 0; g < desc->n_grids; ++g) {
+        const int n = p->grids_host[g].n;
+        for (int cpt : {16, 32, 64, 128}) {
+            if (tile_streamed(n, desc->precision, cpt)) {
+                slot = std::max(slot, streamed_slot_bytes(n, desc->precision));
+                slots = std::max(slots, p->n_cu * solve_wgs_per_cu(n, desc->precision, cpt));
+            }
+        }
+    }
+    if (slots > 0) {
+        p->gws = dmalloc(p, slot * slots, &err);
+        p->gws_slots = slots;
+        if (err != RD_OK) {
+            destroy_problem(p);
+            return err;
+        }
+    }
+    *out = p;
+    return RD_OK;
+}
+
+extern "C" int32_t destroy_problem(rd_problem *p)
+{
+    if (!p)
+        return RD_OK;
+    hipDeviceSynchronize();
+    drop_graphs(p);
+    if (p->sur)
+        surrogate_destroy(p->sur);
+    for (auto &pr : p->pending) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    for (auto e : p->free_events)
+        hipEventDestroy(e);
+    for (void *a : p->allocs)
+        hipFree(a);
+    delete p;
+    return RD_OK;
+}
+
+static int32_t check_batch(rd_problem *p, int32_t n)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    if (n < 0 || n > p->desc.max_batch)
+        return fail(RD_EINVAL, "n = %d outside [0, max_batch=%d]", n, p->desc.max_batch);
+    return RD_OK;
+}
+
+extern "C" int32_t forward_solve_batch(rd_problem *p, int32_t n, const double *theta,
+                                       const int32_t *grid_id, void *u_out, void *v_out,
+                                       int32_t *status, int32_t *cg_iters, void *stream)
+{
+    int32_t r = check_batch(p, n);
+    if (r != RD_OK)
+        return r;
+    if (!status || (n > 0 && !theta))
+        return fail(RD_EINVAL, "theta and status are required");
+    return enqueue_solve(p, n, theta, grid_id, nullptr, nullptr, status, cg_iters, u_out, v_out,
+                         (hipStream_t)stream);
+}
+
+extern "C" int32_t log_likelihood_batch(rd_problem *p, int32_t n, const double *theta,
+                                        const int32_t *grid_id, double *phi, int32_t *status,
+                                        int32_t *cg_iters, void *stream)
+{
+    int32_t r = check_batch(p, n);
+    if (r != RD_OK)
+        return r;
+    if (!status || !phi || (n > 0 && !theta))
+        return fail(RD_EINVAL, "theta, phi and status are required");
+    for (auto &g : p->grids_host)
+        if (!g.y)
+            return fail(RD_EINVAL, "a grid class has no data y");
+    return enqueue_solve(p, n, theta, grid_id, nullptr, phi, status, cg_iters, nullptr, nullptr,
+                         (hipStream_t)stream);
+}
+
+extern "C" int32_t field_misfit_batch(rd_problem *p, int32_t n, const void *u,
+                                      const int32_t *grid_id, double *phi, void *stream)
+{
+    int32_t r = check_batch(p, n);
+    if (r != RD_OK)
+        return r;
+    if (n > 0 && (!u || !phi))
+        return fail(RD_EINVAL, "u and phi are required");
+    if (p->desc.n_grids != 1 && grid_id)
+        return fail(RD_EUNSUPPORTED, "field_misfit_batch takes one grid size");
+    if (!p->grids_host[0].y)
+        return fail(RD_EINVAL, "grid 0 has no data y");
+    const int npts = p->grids_host[0].n * p->grids_host[0].n;
+    HIP_TRY(launch_field_misfit(p->desc.precision, p->grids_dev, grid_id, n, npts, u, phi,
+                                (hipStream_t)stream));
+    return RD_OK;
+}
+
+extern "C" int32_t mcmc_step_batch(rd_problem *p, rd_chains *chains, int32_t n_steps, int32_t mode,
+                                   void *stream)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    if (mode != RD_MODE_PLAIN && mode != RD_MODE_DA)
+        return fail(RD_EINVAL, "mode must be 0 (plain) or 1 (delayed acceptance)");
+    int32_t r = check_chains(p, chains, mode);
+    if (r != RD_OK)
+        return r;
+    if (n_steps < 0)
+        return fail(RD_EINVAL, "n_steps < 0");
+    if (mode == RD_MODE_DA && (!p->sur || !surrogate_ready(p->sur)))
+        return fail(RD_EUNSUPPORTED, "delayed acceptance needs a trained surrogate with scaling");
+    for (auto &g : p->grids_host)
+        if (!g.y)
+            return fail(RD_EINVAL, "a grid class has no data y");
+    if (n_steps == 0 || chains->n_chains == 0) {
+        chains->step += (uint64_t)n_steps;
+        return RD_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->step, s));
+    // Graph capture needs a created stream (the legacy null stream cannot
+    // be captured); the null stream and timing runs use direct launches.
+    const bool graphs = p->use_graphs && !p->timing && s != nullptr;
+    if (!graphs) {
+        for (int k = 0; k < n_steps; ++k)
+            if ((r = enqueue_mcmc_step(p, chains, mode, s)) != RD_OK)
+                return r;
+        chains->step += (uint64_t)n_steps;
+        return RD_OK;
+    }
+    GraphEntry *ge = nullptr;
+    for (auto &g : p->graphs)
+        if (same_chains(g.key, *chains) && g.mode == mode && g.stream == s)
+            ge = &g;
+    int done = 0;
+    if (!ge) {
+        // The first step of a new layout runs as direct launches, so every
+        // kernel of the sequence has been loaded and launched once before
+        // capture begins; capture then records launches only.
+        if ((r = enqueue_mcmc_step(p, chains, mode, s)) != RD_OK)
+            return r;
+        done = 1;
+        if (done == n_steps) {
+            chains->step += (uint64_t)n_steps;
+            return RD_OK;
+        }
+        GraphEntry g;
+        g.key = *chains;
+        g.mode = mode;
+        g.stream = s;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+        r = enqueue_mcmc_step(p, chains, mode, s);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &graph);
+        if (r != RD_OK) {
+            if (graph)
+                hipGraphDestroy(graph);
+            return r;
+        }
+        if (e != hipSuccess)
+            return fail(RD_EHIP, "graph capture: %s", hipGetErrorString(e));
+        g.graph = graph;
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(graph);
+            return fail(RD_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        p->graphs.push_back(g);
+        ge = &p->graphs.back();
+    }
+    for (int k = done; k < n_steps; ++k)
+        HIP_TRY(hipGraphLaunch(ge->exec, s));
+    chains->step += (uint64_t)n_steps;
+    return RD_OK;
+}
+
+extern "C" int32_t propose_batch(rd_problem *p, rd_chains *chains, double *phi_prop,
+                                 int32_t *inside, void *stream)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    int32_t r = check_chains(p, chains, RD_MODE_PLAIN);
+    if (r != RD_OK)
+        return r;
+    if (!phi_prop || !inside)
+        return fail(RD_EINVAL, "phi_prop and inside are required");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->step, s));
+    SamplerArgs a = sampler_args(p, chains);
+    a.phi_prop = phi_prop;
+    a.inside = inside;
+    a.theta_prop = nullptr;
+    HIP_TRY(launch_propose(a, s));
+    return RD_OK;
+}
+
+extern "C" int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *phi_prop,
+                                const int32_t *inside, const double *loglik_prop, void *stream)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    int32_t r = check_chains(p, chains, RD_MODE_PLAIN);
+    if (r != RD_OK)
+        return r;
+    if (!phi_prop || !inside || !loglik_prop)
+        return fail(RD_EINVAL, "phi_prop, inside and loglik_prop are required");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->step, s));
+    SamplerArgs a = sampler_args(p, chains);
+    a.phi_prop = const_cast<double *>(phi_prop);
+    a.inside = const_cast<int *>(inside);
+    a.loglik_prop = loglik_prop;
+    HIP_TRY(launch_accept(a, s));
+    chains->step += 1;
+    return RD_OK;
+}
+
+extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    // Trial: one solve per resident workgroup slot over a short horizon, on
+    // the homogeneous-state parameters of the prior centre.
+    const int trial_steps = std::min(p->desc.n_steps, 40);
+    for (int g = 0; g < p->desc.n_grids; ++g) {
+        const int n = p->grids_host[g].n;
+        int best = p->tile[g].cpt;
+        float best_ms = 1e30f;
+        for (int cpt : {4, 8, 16, 32, 64, 128}) {
+            if (!tile_supported(n, p->desc.precision, cpt) || n * n / cpt > 1024 || n * n / cpt < 64)
+                continue;
+            const int items = std::min(p->desc.max_batch, p->n_cu * solve_wgs_per_cu(n, p->desc.precision, cpt));
+            std::vector<double> th(4 * items);
+            for (int k = 0; k < items; ++k) {
+                th[4 * k + 0] = 0.5 * (p->desc.lo[0] + p->desc.hi[0]);
+                th[4 * k + 1] = 0.5 * (p->desc.lo[1] + p->desc.hi[1]);
+                th[4 * k + 2] = exp(0.5 * (p->desc.lo[2] + p->desc.hi[2]));
+                th[4 * k + 3] = exp(0.5 * (p->desc.lo[3] + p->desc.hi[3]));
+            }
+            double *d_th = nullptr;
+            int *d_st = nullptr;
+            HIP_TRY(hipMalloc(&d_th, sizeof(double) * th.size()));
+            HIP_TRY(hipMalloc(&d_st, sizeof(int) * items));
+            HIP_TRY(hipMemcpy(d_th, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice));
+            const TileChoice saved = p->tile[g];
+            const int saved_wpc = p->wgs_per_cu[g];
+            const int saved_steps = p->desc.n_steps;
+            p->tile[g] = TileChoice{cpt, n * n / cpt};
+            p->wgs_per_cu[g] = solve_wgs_per_cu(n, p->desc.precision, cpt);
+            p->desc.n_steps = trial_steps;
+            hipEvent_t e0, e1;
+            hipEventCreate(&e0);
+            hipEventCreate(&e1);
+            const bool saved_timing = p->timing;
+            p->timing = false;
+            int32_t r = enqueue_solve(p, items, d_th, nullptr, nullptr, nullptr, d_st, nullptr,
+                                      nullptr, nullptr, nullptr);
+            hipEventRecord(e0, nullptr);
+            if (r == RD_OK)
+                r = enqueue_solve(p, items, d_th, nullptr, nullptr, nullptr, d_st, nullptr,
+                                  nullptr, nullptr, nullptr);
+            hipEventRecord(e1, nullptr);
+            hipEventSynchronize(e1);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            p->timing = saved_timing;
+            p->desc.n_steps = saved_steps;
+            p->tile[g] = saved;
+            p->wgs_per_cu[g] = saved_wpc;
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            hipFree(d_th);
+            hipFree(d_st);
+            if (r != RD_OK)
+                return r;
+            // time per item (the slot counts differ between tiles)
+            const float per_item = ms / (float)items;
+            if (per_item < best_ms) {
+                best_ms = per_item;
+                best = cpt;
+            }
+        }
+        p->tile[g] = TileChoice{best, n * n / best};
+        p->wgs_per_cu[g] = solve_wgs_per_cu(n, p->desc.precision, best);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[tune_key(p->device, n, p->desc.precision)] = best;
+        }
+        if (cpt_out)
+            cpt_out[g] = best;
+    }
+    drop_graphs(p);
+    return RD_OK;
+}
+
+extern "C" int32_t rd_solver_timing(rd_problem *p, int32_t enable, double *ms_total,
+                                    int64_t *launches, int32_t reset)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    for (auto &pr : p->pending) {
+        HIP_TRY(hipEventSynchronize(pr.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        p->ms_total += ms;
+        p->launches += 1;
+        p->free_events.push_back(pr.first);
+        p->free_events.push_back(pr.second);
+    }
+    p->pending.clear();
+    if (ms_total)
+        *ms_total = p->ms_total;
+    if (launches)
+        *launches = p->launches;
+    if (reset) {
+        p->ms_total = 0.0;
+        p->launches = 0;
+    }
+    p->timing = enable != 0;
+    return RD_OK;
+}
+
+extern "C" const char *rd_status_string(int32_t s)
+{
+    switch (s) {
+    case RD_OK: return "ok";
+    case RD_EINVAL: return "invalid argument";
+    case RD_EHIP: return "HIP runtime error";
+    case RD_ENOMEM: return "out of device memory";
+    case RD_EUNSUPPORTED: return "unsupported configuration";
+    case RD_ST_NOT_CONVERGED: return "CG not converged";
+    case RD_ST_BREAKDOWN: return "CG breakdown (operator not positive definite)";
+    case RD_ST_NONFINITE: return "non-finite value";
+    case RD_ST_OUT_OF_PRIOR: return "outside the prior box";
+    default: return "combination of status flags";
+    }
+}
+
+extern "C" const char *rd_last_error(void)
+{
+    return g_err;
+}
+
+// ---------------------------------------------------------------------------
+// Surrogate entry points (implemented in rd_mlp.hip).
+
+extern "C" int32_t surrogate_create(rd_problem *p, int32_t width, int32_t depth, int32_t out_side,
+                                    uint32_t seed)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    if (width <= 0 || width % 64 || depth < 1 || depth > 8 || out_side <= 0 ||
+        p->grids_host[0].n % out_side || (out_side * out_side) % 64)
+        return fail(RD_EINVAL, "surrogate shape: width %% 64 == 0, 1 <= depth <= 8, out_side | n");
+    if (p->sur)
+        surrogate_destroy(p->sur);
+    p->sur = nullptr;
+    drop_graphs(p);
+    SurrogateDesc d{};
+    d.width = width;
+    d.depth = depth;
+    d.out_side = out_side;
+    d.n = p->grids_host[0].n;
+    d.precision = p->desc.precision;
+    for (int i = 0; i < 4; ++i) {
+        d.lo[i] = p->desc.lo[i];
+        d.hi[i] = p->desc.hi[i];
+    }
+    d.y = p->grids_host[0].y;
+    d.max_batch = std::max(p->desc.max_batch, 4096);
+    int32_t r = surrogate_new(&p->sur, d, seed);
+    if (r != RD_OK)
+        return fail(r, "surrogate allocation failed");
+    return RD_OK;
+}
+
+extern "C" int32_t downsample_batch(rd_problem *p, int32_t n, const void *u, float *out,
+                                    void *stream)
+{
+    int32_t r = check_batch(p, n);
+    if (r != RD_OK && n <= 0)
+        return r;
+    if (!p || !p->sur)
+        return fail(RD_EINVAL, "downsample_batch needs surrogate_create first");
+    if (n < 0 || (n > 0 && (!u || !out)))
+        return fail(RD_EINVAL, "u and out are required");
+    HIP_TRY(surrogate_downsample(p->sur, n, u, out, (hipStream_t)stream));
+    return RD_OK;
+}
+
+extern "C" int32_t surrogate_set_scaling(rd_problem *p, const float *mean, const float *sd,
+                                         double sigma1, void *stream)
+{
+    if (!p || !p->sur)
+        return fail(RD_EINVAL, "surrogate_set_scaling needs surrogate_create first");
+    if (!mean || !sd || !(sigma1 > 0.0))
+        return fail(RD_EINVAL, "mean, sd and sigma1 > 0 are required");
+    if (!p->grids_host[0].y)
+        return fail(RD_EINVAL, "grid 0 has no data y");
+    HIP_TRY(surrogate_scaling(p->sur, mean, sd, sigma1, (hipStream_t)stream));
+    drop_graphs(p);
+    return RD_OK;
+}
+
+extern "C" int32_t surrogate_train_step(rd_problem *p, int32_t batch, const double *phi,
+                                        const float *target, double lr, double *loss_out,
+                                        void *stream)
+{
+    if (!p || !p->sur)
+        return fail(RD_EINVAL, "surrogate_train_step needs surrogate_create first");
+    if (batch < 1 || batch > surrogate_max_batch(p->sur) || !phi || !target || !(lr > 0.0))
+        return fail(RD_EINVAL, "batch in [1, %d], phi, target and lr > 0 required",
+                    surrogate_max_batch(p->sur));
+    HIP_TRY(surrogate_train(p->sur, batch, phi, target, lr, loss_out, (hipStream_t)stream));
+    return RD_OK;
+}
+
+extern "C" int32_t surrogate_forward(rd_problem *p, int32_t n, const double *phi, float *out,
+                                     int32_t raw, void *stream)
+{
+    if (!p || !p->sur)
+        return fail(RD_EINVAL, "surrogate_forward needs surrogate_create first");
+    if (n < 0 || n > surrogate_max_batch(p->sur) || (n > 0 && (!phi || !out)))
+        return fail(RD_EINVAL, "n in [0, %d], phi and out required", surrogate_max_batch(p->sur));
+    if (!raw && !surrogate_ready(p->sur))
+        return fail(RD_EINVAL, "de-standardised output needs surrogate_set_scaling");
+    HIP_TRY(surrogate_predict(p->sur, n, phi, out, raw, (hipStream_t)stream));
+    return RD_OK;
+}
+
+extern "C" int32_t surrogate_loglik_batch(rd_problem *p, int32_t n, const double *phi,
+                                          double *phi_sur, void *stream)
+{
+    if (!p || !p->sur || !surrogate_ready(p->sur))
+        return fail(RD_EINVAL, "surrogate_loglik_batch needs a surrogate with scaling");
+    if (n < 0 || n > surrogate_max_batch(p->sur) || (n > 0 && (!phi || !phi_sur)))
+        return fail(RD_EINVAL, "n in [0, %d], phi and phi_sur required", surrogate_max_batch(p->sur));
+    int32_t r = surrogate_enqueue_loglik(p->sur, n, phi, phi_sur, (hipStream_t)stream);
+    if (r != RD_OK)
+        return fail(r, "surrogate evaluation failed");
+    return RD_OK;
+}
+
+extern "C" int32_t surrogate_params(rd_problem *p, int32_t layer, float *w, float *b, int32_t dir,
+                                    void *stream)
+{
+    if (!p || !p->sur)
+        return fail(RD_EINVAL, "surrogate_params needs surrogate_create first");
+    if (layer < 0 || layer > surrogate_layers(p->sur) - 1 || (dir != 0 && dir != 1) || !w || !b)
+        return fail(RD_EINVAL, "layer in [0, %d], dir 0/1, w and b required",
+                    surrogate_layers(p->sur) - 1);
+    HIP_TRY(surrogate_copy_params(p->sur, layer, w, b, dir, (hipStream_t)stream));
+    if (dir == 1)
+        drop_graphs(p);
+    return RD_OK;
+}

@@ -1,0 +1,122 @@
+// Device helpers shared by the HIP kernels of the library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rd {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Counter-based generator: Philox4x32 with 10 rounds (Salmon, Moraes, Dror,
+// Shaw, SC 2011).  Each round multiplies words 0 and 2 by the two round
+// multipliers, swaps the halves and folds in the key; the key is bumped by
+// the Weyl constants between rounds.
+struct U32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U32x4 philox10(U32x4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Sampler stream: key = (chain, seed), counter = (step lo, step hi, purpose, block).
+__device__ __forceinline__ U32x4 stream_block(uint32_t seed, uint32_t chain, uint64_t step,
+                                              uint32_t purpose, uint32_t block)
+{
+    return philox10(U32x4{(uint32_t)step, (uint32_t)(step >> 32), purpose, block}, chain, seed);
+}
+
+// (0,1) double from the top 52 bits of hi:lo, centred in its bin (exact).
+__device__ __forceinline__ double unit_open(uint32_t hi, uint32_t lo)
+{
+    const uint64_t k = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return ((double)k + 0.5) * 0x1p-52;
+}
+
+// Box-Muller pair from one Philox block.
+__device__ __forceinline__ void gauss_pair(U32x4 w, double &z0, double &z1)
+{
+    const double u1 = unit_open(w.x, w.y);
+    const double u2 = unit_open(w.z, w.w);
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 6.283185307179586476925286766559 * u2;
+    double s, c;
+    sincos(ang, &s, &c);
+    z0 = rad * c;
+    z1 = rad * s;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.  The xor butterfly leaves the bit-identical sum in every lane
+// (IEEE addition is commutative, and each level pairs the same two partial
+// sums on both partner lanes), so every thread takes the same branch on it.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Workgroup sum of one value per thread.  `slot` points to kWaves doubles of
+// LDS that no other live reduction uses; callers alternate slots so that a
+// slot is rewritten only after a later barrier.  Ends with every thread
+// holding the same value, summed over waves in a fixed order.  The barrier
+// inside is also what orders the caller's earlier LDS reads before its later
+// LDS writes (even for a single wave), and callers rely on it.
+template <int kWaves>
+__device__ __forceinline__ double block_sum(double v, double *slot)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    if (lane == 0)
+        slot[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w)
+        s += slot[w];
+    return s;
+}
+
+template <int kWaves>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *slot)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        slot[wid] = a;
+        slot[kWaves + wid] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        sa += slot[w];
+        sb += slot[kWaves + w];
+    }
+    a = sa;
+    b = sb;
+}
+
+__device__ __forceinline__ bool finite(double x)
+{
+    return __builtin_isfinite(x);
+}
+
+}  // namespace rd

@@ -1,0 +1,68 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rd {
+
+enum : int { kStNotConverged = 1, kStBreakdown = 2, kStNonfinite = 4, kStOutOfPrior = 8 };
+
+// One grid class as the kernels see it (device memory).
+struct GridDev {
+    int n;             // cells per side
+    int growth;        // 0 stationary, 1 rho = exp(rate t)
+    double rate;       // growth rate r
+    const void *u0;    // [n*n] initial u in the problem precision
+    const void *v0;    // [n*n] initial v
+    const double *y;   // [n*n] data (float64) or null
+    double inv_2s2;    // 1 / (2 sigma^2)
+    double cost;       // relative cost of one solve (for queue ordering)
+    double dil;        // 2 r (set on the device by k_grid_coeffs)
+    double decay;      // exp(-2 r dt) (set on the device by k_grid_coeffs)
+};
+
+// Arguments of one fused solve launch.
+struct SolveArgs {
+    const GridDev *grids;    // device array [n_grids]
+    int n_items;             // queue length
+    const int *order;        // item -> index into the batch (null: identity)
+    const int *grid_id;      // batch index -> grid class (null: 0)
+    const double *theta;     // [n][4] natural parameters (a, b, gamma, d)
+    const int *need;         // [n] nonzero: solve this index (null: all)
+    double dt;
+    int n_steps;
+    double rtol2;            // cg_rtol^2
+    int maxit;
+    double *phi;             // [n] misfit out (null: skip misfit)
+    int *status;             // [n] status out (required)
+    int *iters;              // [n][2] CG iteration totals (null: skip)
+    void *u_out;             // [n][N*N] final u (null: skip)
+    void *v_out;             // [n][N*N] final v (null: skip)
+    unsigned *queue;         // work-queue head (zeroed before the launch)
+    void *gws;               // global workspace for the streamed (n = 256) variant
+    int gws_slots;           // number of per-workgroup slots in gws
+};
+
+// Solver tile choices: cells per thread (rows of the strip a thread owns).
+struct TileChoice {
+    int cpt;      // cells per thread
+    int threads;  // workgroup size = n*n / cpt
+};
+
+// Host launchers (rd_solver.hip).
+hipError_t launch_solve(int n, int precision, TileChoice tile, const SolveArgs &a, int grid_wgs,
+                        hipStream_t s);
+hipError_t launch_solve_mixed(int precision, const SolveArgs &a, int grid_wgs, hipStream_t s);
+bool tile_supported(int n, int precision, int cpt);
+bool tile_streamed(int n, int precision, int cpt);
+int solve_wgs_per_cu(int n, int precision, int cpt);
+int default_cpt(int n, int precision);
+size_t streamed_slot_bytes(int n, int precision);
+hipError_t launch_fill_u32(unsigned *p, unsigned v, int count, hipStream_t s);
+hipError_t launch_grid_coeffs(GridDev *grids, int n_grids, double dt, hipStream_t s);
+
+// Misfit of given fields (rd_sampler.hip).
+hipError_t launch_field_misfit(int precision, const GridDev *grids, const int *grid_id, int n,
+                               int npts, const void *u, double *phi, hipStream_t s);
+
+}  // namespace rd

@@ -1,0 +1,229 @@
+// Per-chain random-walk Metropolis kernels (Sec. 2, Algorithm 1) and the
+// stand-alone misfit kernel.  One thread per chain; every floating-point
+// decision is taken in FP64.
+#include "rd_device.hpp"
+#include "rd_internal.hpp"
+#include "rd_sampler.hpp"
+
+// Proposal arithmetic is kept free of fused multiply-adds so that phi' is
+// the correctly rounded phi + (s * z) of its definition.
+#pragma clang fp contract(off)
+
+namespace rd {
+
+enum : uint32_t { kPurposeProposal = 0, kPurposeAccept = 1, kPurposeStage1 = 2 };
+
+// phi' = phi + s .* z (free coordinates), z ~ N(0, I); inside = every
+// coordinate within [lo, hi]; theta' = (a, b, exp(ln gamma), exp(ln d)).
+__global__ void k_propose(SamplerArgs a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n)
+        return;
+    const uint64_t step = a.ctr[0];
+    double z[4];
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, kPurposeProposal, 0), z[0], z[1]);
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, kPurposeProposal, 1), z[2], z[3]);
+    double p[4];
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        p[i] = a.phi[4 * c + i];
+        if ((a.cfg.free_mask >> i) & 1u)
+            p[i] = p[i] + a.cfg.step[i] * z[i];
+        in = in && (a.cfg.lo[i] <= p[i]) && (p[i] <= a.cfg.hi[i]);
+        a.phi_prop[4 * c + i] = p[i];
+    }
+    if (a.theta_prop) {
+        a.theta_prop[4 * c + 0] = p[0];
+        a.theta_prop[4 * c + 1] = p[1];
+        a.theta_prop[4 * c + 2] = exp(p[2]);
+        a.theta_prop[4 * c + 3] = exp(p[3]);
+    }
+    a.inside[c] = in ? 1 : 0;
+}
+
+// Accept iff log U < Phi(phi) - Phi(phi'), U from purpose 1; then record.
+__global__ void k_accept(SamplerArgs a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n)
+        return;
+    const uint64_t step = a.ctr[0];
+    bool acc = false;
+    if (a.inside[c]) {
+        const U32x4 w = stream_block(a.seed, (uint32_t)c, step, kPurposeAccept, 0);
+        const double u = unit_open(w.x, w.y);
+        acc = log(u) < a.loglik[c] - a.loglik_prop[c];
+        if (a.n_solves)
+            a.n_solves[c] += 1;
+    }
+    if (acc) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a.phi[4 * c + i] = a.phi_prop[4 * c + i];
+        a.loglik[c] = a.loglik_prop[c];
+        if (a.n_accept)
+            a.n_accept[c] += 1;
+    }
+    if (a.trace) {
+        const uint64_t row = step - a.ctr[1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a.trace[(row * (uint64_t)a.n + c) * 4 + i] = a.phi[4 * c + i];
+    }
+}
+
+// Delayed acceptance, first stage: log U1 < Phi~(phi) - Phi~(phi'), U1 from
+// purpose 2.  Writes need[c] (solve the proposal) and counts stage-1 accepts.
+__global__ void k_da_stage1(SamplerArgs a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n)
+        return;
+    const uint64_t step = a.ctr[0];
+    bool acc1 = false;
+    if (a.inside[c]) {
+        const U32x4 w = stream_block(a.seed, (uint32_t)c, step, kPurposeStage1, 0);
+        const double u = unit_open(w.x, w.y);
+        acc1 = log(u) < a.loglik_sur[c] - a.loglik_sur_prop[c];
+    }
+    a.need[c] = acc1 ? 1 : 0;
+    if (acc1 && a.n_accept1)
+        a.n_accept1[c] += 1;
+}
+
+// Second stage: log U2 < [Phi(phi) - Phi(phi')] - [Phi~(phi) - Phi~(phi')].
+__global__ void k_da_stage2(SamplerArgs a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n)
+        return;
+    const uint64_t step = a.ctr[0];
+    bool acc = false;
+    if (a.need[c]) {
+        const U32x4 w = stream_block(a.seed, (uint32_t)c, step, kPurposeAccept, 0);
+        const double u = unit_open(w.x, w.y);
+        const double la = (a.loglik[c] - a.loglik_prop[c]) - (a.loglik_sur[c] - a.loglik_sur_prop[c]);
+        acc = log(u) < la;
+        if (a.n_solves)
+            a.n_solves[c] += 1;
+    }
+    if (acc) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a.phi[4 * c + i] = a.phi_prop[4 * c + i];
+        a.loglik[c] = a.loglik_prop[c];
+        a.loglik_sur[c] = a.loglik_sur_prop[c];
+        if (a.n_accept)
+            a.n_accept[c] += 1;
+    }
+    if (a.trace) {
+        const uint64_t row = step - a.ctr[1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a.trace[(row * (uint64_t)a.n + c) * 4 + i] = a.phi[4 * c + i];
+    }
+}
+
+__global__ void k_set_ctr(uint64_t *ctr, uint64_t step, uint64_t step0)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctr[0] = step;
+        ctr[1] = step0;
+    }
+}
+
+__global__ void k_advance_ctr(uint64_t *ctr)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        ctr[0] = ctr[0] + 1;
+}
+
+// inside -> need copy (plain sampler: solve every in-box proposal).
+__global__ void k_copy_i32(const int *src, int *dst, int n)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n)
+        dst[c] = src[c];
+}
+
+template <typename Real>
+__global__ void k_field_misfit(const GridDev *grids, const int *grid_id, int npts, const Real *u,
+                               double *phi)
+{
+    __shared__ double red[4];
+    const int c = blockIdx.x;
+    const GridDev &gd = grids[grid_id ? grid_id[c] : 0];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < npts; k += blockDim.x) {
+        const double e = gd.y[k] - (double)u[(size_t)c * npts + k];
+        s += e * e;
+    }
+    s = block_sum<4>(s, red);
+    if (threadIdx.x == 0)
+        phi[c] = finite(s) ? s * gd.inv_2s2 : __builtin_inf();
+}
+
+static inline dim3 chain_blocks(int n)
+{
+    return dim3((n + 255) / 256);
+}
+
+hipError_t launch_propose(const SamplerArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_propose, chain_blocks(a.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_accept(const SamplerArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_accept, chain_blocks(a.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_da_stage1(const SamplerArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_da_stage1, chain_blocks(a.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_da_stage2(const SamplerArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_da_stage2, chain_blocks(a.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_ctr(uint64_t *ctr, uint64_t step, uint64_t step0, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(64), 0, s, ctr, step, step0);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_ctr(uint64_t *ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance_ctr, dim3(1), dim3(64), 0, s, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i32(const int *src, int *dst, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_i32, chain_blocks(n), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_misfit(int precision, const GridDev *grids, const int *grid_id, int n,
+                               int npts, const void *u, double *phi, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_field_misfit<float>, dim3(n), dim3(256), 0, s, grids, grid_id, npts,
+                           (const float *)u, phi);
+    else
+        hipLaunchKernelGGL(k_field_misfit<double>, dim3(n), dim3(256), 0, s, grids, grid_id, npts,
+                           (const double *)u, phi);
+    return hipGetLastError();
+}
+
+}  // namespace rd

@@ -1,0 +1,41 @@
+// Sampler kernel arguments (shared by rd_sampler.hip and the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rd {
+
+struct SamplerCfg {
+    uint32_t free_mask;
+    double lo[4], hi[4], step[4];
+};
+
+struct SamplerArgs {
+    int n;                        // chains
+    uint32_t seed;
+    const uint64_t *ctr;          // [0] = current step, [1] = step of trace row 0
+    SamplerCfg cfg;
+    double *phi;                  // [n][4] state (sampling coordinates)
+    double *loglik;               // [n] Phi(state)
+    double *loglik_sur;           // [n] Phi~(state) (DA)
+    double *phi_prop;             // [n][4] proposal
+    double *theta_prop;           // [n][4] proposal in natural parameters (or null)
+    int *inside;                  // [n] proposal in the prior box
+    int *need;                    // [n] proposal goes to the full solve
+    const double *loglik_prop;    // [n] Phi(proposal)
+    const double *loglik_sur_prop;// [n] Phi~(proposal)
+    uint64_t *n_accept;
+    uint64_t *n_accept1;
+    uint64_t *n_solves;
+    double *trace;                // [rows][n][4] or null
+};
+
+hipError_t launch_propose(const SamplerArgs &a, hipStream_t s);
+hipError_t launch_accept(const SamplerArgs &a, hipStream_t s);
+hipError_t launch_da_stage1(const SamplerArgs &a, hipStream_t s);
+hipError_t launch_da_stage2(const SamplerArgs &a, hipStream_t s);
+hipError_t launch_set_ctr(uint64_t *ctr, uint64_t step, uint64_t step0, hipStream_t s);
+hipError_t launch_advance_ctr(uint64_t *ctr, hipStream_t s);
+hipError_t launch_copy_i32(const int *src, int *dst, int n, hipStream_t s);
+
+}  // namespace rd
