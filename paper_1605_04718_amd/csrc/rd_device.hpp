@@ -58,6 +58,25 @@ __device__ __forceinline__ void gauss_pair(U32x4 w, double &z0, double &z1)
     z1 = rad * s;
 }
 
+// Wave-uniform copies (scalar registers).  Every value that decides a branch
+// around a barrier goes through one of these: the compiler then lowers the
+// branch as a scalar (uniform) branch.  Without it, loops whose exit depends
+// on an LDS-read value are lowered as exec-masked loops, and the control-flow
+// structurizer may let some lanes of a wave leave such a loop while the rest
+// of the wave passes the next s_barrier (which counts waves, not lanes).
+__device__ __forceinline__ int uniform(int x)
+{
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ __forceinline__ double uniform(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
 // Reductions.  The xor butterfly leaves the bit-identical sum in every lane
 // (IEEE addition is commutative, and each level pairs the same two partial
@@ -89,7 +108,7 @@ __device__ __forceinline__ double block_sum(double v, double *slot)
 #pragma unroll
     for (int w = 0; w < kWaves; ++w)
         s += slot[w];
-    return s;
+    return uniform(s);
 }
 
 template <int kWaves>
@@ -110,13 +129,15 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *slot)
         sa += slot[w];
         sb += slot[kWaves + w];
     }
-    a = sa;
-    b = sb;
+    a = uniform(sa);
+    b = uniform(sb);
 }
 
 __device__ __forceinline__ bool finite(double x)
 {
     return __builtin_isfinite(x);
 }
+
+
 
 }  // namespace rd

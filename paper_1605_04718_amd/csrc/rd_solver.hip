@@ -282,15 +282,16 @@ __device__ void finish_item(const SolveArgs &a, const GridDev &gd, int c, Arr &x
     }
 }
 
-// Pull the next queue item; every thread gets the same value.
+// Pull the next queue item; every thread gets the same (scalar) value.
+// The leading barrier keeps thread 0 from overwriting the slot before every
+// wave has read the previous item.
 __device__ __forceinline__ int next_item(unsigned *queue, int *s_item)
 {
+    __syncthreads();
     if (threadIdx.x == 0)
         *s_item = (int)atomicAdd(queue, 1u);
     __syncthreads();
-    const int item = *s_item;
-    __syncthreads();
-    return item;
+    return uniform(*s_item);
 }
 
 template <int N, int R, typename Real>
@@ -302,28 +303,26 @@ __global__ __launch_bounds__(N *N / R) void k_solve_resident(SolveArgs a)
     __shared__ double red[Slots<NW>::total];
     __shared__ int s_item;
     const Geo<N, R> g;
-    for (;;) {
-        const int item = next_item(a.queue, &s_item);
-        if (item >= a.n_items)
-            break;
-        const int c = a.order ? a.order[item] : item;
-        if (a.need && !a.need[c])
-            continue;
-        const GridDev &gd = a.grids[a.grid_id ? a.grid_id[c] : 0];
-        const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
-                              a.theta[4 * c + 3]};
-        RegArr<Real, R> xu, xv, eu, ev, r, q;
-        const Real *u0 = (const Real *)gd.u0;
-        const Real *v0 = (const Real *)gd.v0;
+    for (int item = next_item(a.queue, &s_item); item < a.n_items;
+         item = next_item(a.queue, &s_item)) {
+        const int c = uniform(a.order ? a.order[item] : item);
+        if (!a.need || uniform(a.need[c])) {
+            const GridDev &gd = a.grids[uniform(a.grid_id ? a.grid_id[c] : 0)];
+            const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
+                                  a.theta[4 * c + 3]};
+            RegArr<Real, R> xu, xv, eu, ev, r, q;
+            const Real *u0 = (const Real *)gd.u0;
+            const Real *v0 = (const Real *)gd.v0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-            xu[k] = u0[g.idx(k)];
-            xv[k] = v0[g.idx(k)];
+            for (int k = 0; k < R; ++k) {
+                xu[k] = u0[g.idx(k)];
+                xv[k] = v0[g.idx(k)];
+            }
+            int itu = 0, itv = 0;
+            const int st = integrate<N, R, R, NW>(xu, xv, eu, ev, r, q, th, gd, a.dt, a.n_steps,
+                                                  a.rtol2, a.maxit, P, stash, red, g, itu, itv);
+            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, g, red);
         }
-        int itu = 0, itv = 0;
-        const int st = integrate<N, R, R, NW>(xu, xv, eu, ev, r, q, th, gd, a.dt, a.n_steps,
-                                              a.rtol2, a.maxit, P, stash, red, g, itu, itv);
-        finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, g, red);
     }
 }
 
@@ -342,47 +341,27 @@ __global__ __launch_bounds__(N *N / R) void k_solve_streamed(SolveArgs a)
     GlobArr<Real, N> xu{slot + base}, xv{slot + (size_t)N * N + base},
         eu{slot + 2 * (size_t)N * N + base}, ev{slot + 3 * (size_t)N * N + base},
         r{slot + 4 * (size_t)N * N + base}, q{slot + 5 * (size_t)N * N + base};
-    for (;;) {
-        const int item = next_item(a.queue, &s_item);
-        if (item >= a.n_items)
-            break;
-        const int c = a.order ? a.order[item] : item;
-        if (a.need && !a.need[c])
-            continue;
-        const GridDev &gd = a.grids[a.grid_id ? a.grid_id[c] : 0];
-        const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
-                              a.theta[4 * c + 3]};
-        const Real *u0 = (const Real *)gd.u0;
-        const Real *v0 = (const Real *)gd.v0;
+    for (int item = next_item(a.queue, &s_item); item < a.n_items;
+         item = next_item(a.queue, &s_item)) {
+        const int c = uniform(a.order ? a.order[item] : item);
+        if (!a.need || uniform(a.need[c])) {
+            const GridDev &gd = a.grids[uniform(a.grid_id ? a.grid_id[c] : 0)];
+            const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
+                                  a.theta[4 * c + 3]};
+            const Real *u0 = (const Real *)gd.u0;
+            const Real *v0 = (const Real *)gd.v0;
 #pragma unroll U
-        for (int k = 0; k < R; ++k) {
-            xu[k] = u0[g.idx(k)];
-            xv[k] = v0[g.idx(k)];
+            for (int k = 0; k < R; ++k) {
+                xu[k] = u0[g.idx(k)];
+                xv[k] = v0[g.idx(k)];
+            }
+            int itu = 0, itv = 0;
+            const int st = integrate<N, R, U, NW>(xu, xv, eu, ev, r, q, th, gd, a.dt, a.n_steps,
+                                                  a.rtol2, a.maxit, P, (Real *)nullptr, red, g,
+                                                  itu, itv);
+            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, g, red);
         }
-        int itu = 0, itv = 0;
-        const int st = integrate<N, R, U, NW>(xu, xv, eu, ev, r, q, th, gd, a.dt, a.n_steps,
-                                              a.rtol2, a.maxit, P, (Real *)nullptr, red, g, itu,
-                                              itv);
-        finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, g, red);
     }
-}
-
-// Per-class time-stepping coefficients of the growing domain rho = exp(r t):
-// dilution m rho'/rho = 2 r and the per-step factor of rho^-2, exp(-2 r dt).
-__global__ void k_grid_coeffs(GridDev *grids, int n_grids, double dt)
-{
-    const int g = threadIdx.x;
-    if (g < n_grids) {
-        const double r = grids[g].growth ? grids[g].rate : 0.0;
-        grids[g].dil = 2.0 * r;
-        grids[g].decay = exp(-2.0 * r * dt);
-    }
-}
-
-hipError_t launch_grid_coeffs(GridDev *grids, int n_grids, double dt, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_grid_coeffs, dim3(1), dim3(64), 0, s, grids, n_grids, dt);
-    return hipGetLastError();
 }
 
 __global__ void k_fill_u32(unsigned *p, unsigned v, int count)
