@@ -364,6 +364,24 @@ __global__ __launch_bounds__(N *N / R) void k_solve_streamed(SolveArgs a)
     }
 }
 
+// Per-class time-stepping coefficients of the growing domain rho = exp(r t):
+// dilution m rho'/rho = 2 r and the per-step factor of rho^-2, exp(-2 r dt).
+__global__ void k_grid_coeffs(GridDev *grids, int n_grids, double dt)
+{
+    const int g = threadIdx.x;
+    if (g < n_grids) {
+        const double r = grids[g].growth ? grids[g].rate : 0.0;
+        grids[g].dil = 2.0 * r;
+        grids[g].decay = exp(-2.0 * r * dt);
+    }
+}
+
+hipError_t launch_grid_coeffs(GridDev *grids, int n_grids, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grid_coeffs, dim3(1), dim3(64), 0, s, grids, n_grids, dt);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_u32(unsigned *p, unsigned v, int count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
