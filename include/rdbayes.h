@@ -122,6 +122,7 @@ int32_t destroy_problem(rd_problem *p);
  *   status   dev int32 [n] RD_ST_* bits (0 = success), required
  *   cg_iters dev int32 [n][2] total CG iterations of the u and v systems,
  *            or NULL
+ * n = 0 is a no-op (array arguments may then be NULL).
  * Errors: RD_EINVAL (n < 0 or n > max_batch, NULL status, mixed sizes with
  * field outputs). */
 int32_t forward_solve_batch(rd_problem *p, int32_t n, const double *theta,
@@ -154,6 +155,8 @@ typedef struct {
     uint64_t *n_accept;    /* dev [n] accepted proposals */
     uint64_t *n_accept1;   /* dev [n] first-stage accepts (DA), or NULL */
     uint64_t *n_solves;    /* dev [n] forward solves performed */
+    uint64_t *cg_iters;    /* dev [n][2] CG iterations (u, v) summed over those
+                              solves, or NULL */
     double *trace;         /* dev [n_steps][n][4] states after each step, or NULL */
     uint32_t seed;         /* Philox key word 1 (key word 0 = chain index) */
     uint64_t step;         /* index of the next step; advanced by the calls */

@@ -38,6 +38,7 @@ class ProblemDesc(ctypes.Structure):
 class Chains(ctypes.Structure):
     _fields_ = [("n_chains", c_i32), ("phi", c_vp), ("loglik", c_vp), ("loglik_sur", c_vp),
                 ("grid_id", c_vp), ("n_accept", c_vp), ("n_accept1", c_vp), ("n_solves", c_vp),
+                ("cg_iters", c_vp),
                 ("trace", c_vp), ("seed", c_u32), ("step", c_u64)]
 
 

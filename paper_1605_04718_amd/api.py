@@ -194,6 +194,7 @@ class ChainState:
     n_accept: torch.Tensor | None = None
     n_accept1: torch.Tensor | None = None
     n_solves: torch.Tensor | None = None
+    cg_iters: torch.Tensor | None = None
     trace: torch.Tensor | None = None
 
     @property
@@ -208,6 +209,7 @@ class ChainState:
         return cls(phi=phi.contiguous(), loglik=loglik.contiguous(), seed=seed, step=step,
                    loglik_sur=torch.zeros(n, dtype=torch.float64, device=dev) if da else None,
                    grid_id=grid_id, n_accept=z(), n_accept1=z(), n_solves=z(),
+                   cg_iters=torch.zeros((n, 2), dtype=torch.int64, device=dev),
                    trace=(torch.zeros((trace_steps, n, 4), dtype=torch.float64, device=dev)
                           if trace_steps else None))
 
@@ -221,6 +223,7 @@ class ChainState:
         c.n_accept = _ptr(self.n_accept)
         c.n_accept1 = _ptr(self.n_accept1)
         c.n_solves = _ptr(self.n_solves)
+        c.cg_iters = _ptr(self.cg_iters)
         c.trace = _ptr(self.trace)
         c.seed = self.seed
         c.step = self.step

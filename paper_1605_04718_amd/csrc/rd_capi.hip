@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -80,6 +81,7 @@ struct rd_problem {
     double *ll_prop = nullptr;
     double *ll_sur_prop = nullptr;
     int *status_ws = nullptr;
+    int *iters_ws = nullptr;
     uint64_t *ctr = nullptr;
     void *gws = nullptr;
     int gws_slots = 0;
@@ -252,6 +254,8 @@ SamplerArgs sampler_args(rd_problem *p, const rd_chains *c)
     a.n_accept = c->n_accept;
     a.n_accept1 = c->n_accept1;
     a.n_solves = c->n_solves;
+    a.cg_iters = c->cg_iters;
+    a.iters = p->iters_ws;
     a.trace = c->trace;
     return a;
 }
@@ -270,7 +274,7 @@ int32_t enqueue_mcmc_step(rd_problem *p, const rd_chains *c, int mode, hipStream
         HIP_TRY(launch_da_stage1(a, s));
     }
     int32_t r = enqueue_solve(p, c->n_chains, p->theta_prop, c->grid_id, p->need, p->ll_prop,
-                              p->status_ws, nullptr, nullptr, nullptr, s);
+                              p->status_ws, p->iters_ws, nullptr, nullptr, s);
     if (r != RD_OK)
         return r;
     if (mode == RD_MODE_PLAIN)
@@ -285,7 +289,8 @@ bool same_chains(const rd_chains &a, const rd_chains &b)
 {
     return a.n_chains == b.n_chains && a.phi == b.phi && a.loglik == b.loglik &&
            a.loglik_sur == b.loglik_sur && a.grid_id == b.grid_id && a.n_accept == b.n_accept &&
-           a.n_accept1 == b.n_accept1 && a.n_solves == b.n_solves && a.trace == b.trace &&
+           a.n_accept1 == b.n_accept1 && a.n_solves == b.n_solves && a.cg_iters == b.cg_iters &&
+           a.trace == b.trace &&
            a.seed == b.seed;
 }
 
@@ -393,6 +398,7 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     p->ll_prop = (double *)dmalloc(p, sizeof(double) * B, &err);
     p->ll_sur_prop = (double *)dmalloc(p, sizeof(double) * B, &err);
     p->status_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
+    p->iters_ws = (int *)dmalloc(p, sizeof(int) * 2 * B, &err);
     if (err != RD_OK) {
         destroy_problem(p);
         return err;
@@ -465,7 +471,7 @@ extern "C" int32_t forward_solve_batch(rd_problem *p, int32_t n, const double *t
     int32_t r = check_batch(p, n);
     if (r != RD_OK)
         return r;
-    if (!status || (n > 0 && !theta))
+    if (n > 0 && (!status || !theta))
         return fail(RD_EINVAL, "theta and status are required");
     return enqueue_solve(p, n, theta, grid_id, nullptr, nullptr, status, cg_iters, u_out, v_out,
                          (hipStream_t)stream);
@@ -478,7 +484,7 @@ extern "C" int32_t log_likelihood_batch(rd_problem *p, int32_t n, const double *
     int32_t r = check_batch(p, n);
     if (r != RD_OK)
         return r;
-    if (!status || !phi || (n > 0 && !theta))
+    if (n > 0 && (!status || !phi || !theta))
         return fail(RD_EINVAL, "theta, phi and status are required");
     for (auto &g : p->grids_host)
         if (!g.y)
@@ -620,6 +626,7 @@ extern "C" int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *
     a.phi_prop = const_cast<double *>(phi_prop);
     a.inside = const_cast<int *>(inside);
     a.loglik_prop = loglik_prop;
+    a.iters = nullptr;  // the caller's Phi did not come from this library's solve
     HIP_TRY(launch_accept(a, s));
     chains->step += 1;
     return RD_OK;
@@ -685,6 +692,10 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
                 return r;
             // time per item (the slot counts differ between tiles)
             const float per_item = ms / (float)items;
+            if (getenv("RDBAYES_AUTOTUNE_VERBOSE"))
+                fprintf(stderr, "[rd_autotune] n=%d prec=%d cpt=%d threads=%d wgs/cu=%d: %.4f ms/item\n",
+                        n, p->desc.precision, cpt, n * n / cpt,
+                        solve_wgs_per_cu(n, p->desc.precision, cpt), per_item);
             if (per_item < best_ms) {
                 best_ms = per_item;
                 best = cpt;

@@ -78,30 +78,40 @@ __device__ __forceinline__ double uniform(double x)
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  The xor butterfly leaves the bit-identical sum in every lane
-// (IEEE addition is commutative, and each level pairs the same two partial
-// sums on both partner lanes), so every thread takes the same branch on it.
-__device__ __forceinline__ double wave_sum(double v)
+// Reductions.  A wave sums its 64 lanes with DPP moves (no LDS traffic):
+// four row_shr steps leave each 16-lane row's sum in its lane 15, then
+// row_bcast:15 and row_bcast:31 fold the rows into lane 63.  The order of
+// additions is fixed, so the result is deterministic.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1)
-        v += __shfl_xor(v, off, kWave);
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, kRowMask, 0xF, true);
+    const int hi =
+        __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl, kRowMask, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+constexpr int kLastLane = kWave - 1;
+
+__device__ __forceinline__ double wave_sum_last_lane(double v)
+{
+    v += dpp_f64<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_f64<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_f64<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_f64<0x118, 0xF>(v);  // row_shr:8  -> lane 15 of each row: row sum
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3 -> lane 63: total
     return v;
 }
 
-// Workgroup sum of one value per thread.  `slot` points to kWaves doubles of
-// LDS that no other live reduction uses; callers alternate slots so that a
-// slot is rewritten only after a later barrier.  Ends with every thread
-// holding the same value, summed over waves in a fixed order.  The barrier
-// inside is also what orders the caller's earlier LDS reads before its later
-// LDS writes (even for a single wave), and callers rely on it.
 template <int kWaves>
 __device__ __forceinline__ double block_sum(double v, double *slot)
 {
-    v = wave_sum(v);
+    v = wave_sum_last_lane(v);
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    if (lane == 0)
+    if (lane == kLastLane)
         slot[wid] = v;
     __syncthreads();
     double s = 0.0;
@@ -114,11 +124,11 @@ __device__ __forceinline__ double block_sum(double v, double *slot)
 template <int kWaves>
 __device__ __forceinline__ void block_sum2(double &a, double &b, double *slot)
 {
-    a = wave_sum(a);
-    b = wave_sum(b);
+    a = wave_sum_last_lane(a);
+    b = wave_sum_last_lane(b);
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    if (lane == 0) {
+    if (lane == kLastLane) {
         slot[wid] = a;
         slot[kWaves + wid] = b;
     }

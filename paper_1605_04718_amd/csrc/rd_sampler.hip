@@ -57,6 +57,10 @@ __global__ void k_accept(SamplerArgs a)
         acc = log(u) < a.loglik[c] - a.loglik_prop[c];
         if (a.n_solves)
             a.n_solves[c] += 1;
+        if (a.cg_iters && a.iters) {
+            a.cg_iters[2 * c] += (uint64_t)a.iters[2 * c];
+            a.cg_iters[2 * c + 1] += (uint64_t)a.iters[2 * c + 1];
+        }
     }
     if (acc) {
 #pragma unroll
@@ -108,6 +112,10 @@ __global__ void k_da_stage2(SamplerArgs a)
         acc = log(u) < la;
         if (a.n_solves)
             a.n_solves[c] += 1;
+        if (a.cg_iters && a.iters) {
+            a.cg_iters[2 * c] += (uint64_t)a.iters[2 * c];
+            a.cg_iters[2 * c + 1] += (uint64_t)a.iters[2 * c + 1];
+        }
     }
     if (acc) {
 #pragma unroll

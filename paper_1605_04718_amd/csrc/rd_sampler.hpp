@@ -27,6 +27,8 @@ struct SamplerArgs {
     uint64_t *n_accept;
     uint64_t *n_accept1;
     uint64_t *n_solves;
+    uint64_t *cg_iters;           // [n][2] accumulated CG iterations or null
+    const int *iters;             // [n][2] CG iterations of this step's solves
     double *trace;                // [rows][n][4] or null
 };
 

@@ -117,15 +117,23 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
 
     // r0 = b - A x0 = src - e x0 - c t(x0): the 1/dt terms cancel exactly,
     // so r0 (the scaled time derivative) keeps full relative precision.
-    double bb = 0.0, rr = 0.0;
+    // Two interleaved FP64 partial sums per dot product halve the dependent
+    // accumulation chains.
+    double bb0 = 0.0, bb1 = 0.0, rr0 = 0.0, rr1 = 0.0;
     sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
         const Real b = own * inv_dt + src;
         const Real res = src - es[k] * own - c * t;
         r[k] = res;
         es[k] = es[k] + inv_dt;
-        bb += (double)b * (double)b;
-        rr += (double)res * (double)res;
+        if (k & 1) {
+            bb1 += (double)b * (double)b;
+            rr1 += (double)res * (double)res;
+        } else {
+            bb0 += (double)b * (double)b;
+            rr0 += (double)res * (double)res;
+        }
     });
+    double bb = bb0 + bb1, rr = rr0 + rr1;
     block_sum2<NW>(bb, rr, red + Slots<NW>::setup);
 #pragma unroll U
     for (int k = 0; k < R; ++k) {
@@ -142,13 +150,16 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
             break;
         }
         __syncthreads();  // p visible to the neighbours
-        double pq = 0.0;
+        double pq0 = 0.0, pq1 = 0.0;
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
             const Real qq = c * t + es[k] * own;
             q[k] = qq;
-            pq += (double)own * (double)qq;
+            if (k & 1)
+                pq1 += (double)own * (double)qq;
+            else
+                pq0 += (double)own * (double)qq;
         });
-        pq = block_sum<NW>(pq, red + Slots<NW>::pq);
+        const double pq = block_sum<NW>(pq0 + pq1, red + Slots<NW>::pq);
         if (!finite(pq)) {
             st = kStNonfinite;
             break;
@@ -159,15 +170,18 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
         }
         const double alpha = rr / pq;
         const Real a = (Real)alpha;
-        double rn = 0.0;
+        double rn0 = 0.0, rn1 = 0.0;
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
             const Real v = r[k] - a * q[k];
             r[k] = v;
-            rn += (double)v * (double)v;
+            if (k & 1)
+                rn1 += (double)v * (double)v;
+            else
+                rn0 += (double)v * (double)v;
             RD_GROUP_FENCE(k)
         }
-        rn = block_sum<NW>(rn, red + Slots<NW>::rr);
+        const double rn = block_sum<NW>(rn0 + rn1, red + Slots<NW>::rr);
         ++it;
         if (!finite(rn)) {
             st = kStNonfinite;
