@@ -78,7 +78,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chains", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=500)
+    ap.add_argument("--cpu-sample-steps", type=int, default=2000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device (a known-size kernel that scales "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the chains are independent and shard across GPUs "
@@ -92,6 +95,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read and written once")
+        del src, dst
     n_steps = int(round(T_FINAL / TAU))
     C = args.chains
     step = tuple(0.02 * (h - l) for l, h in zip(LO, HI))
@@ -108,6 +119,8 @@ def main():
 
     p = Problem([Grid(n=N_CELLS, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, n_steps, CG_RTOL,
                 cg_maxit=CG_MAXIT, lo=LO, hi=HI, step=step, max_batch=C)
+    cpt = p.autotune()[0]
+    log(f"autotuned tile: {cpt} cells per thread ({N_CELLS * N_CELLS // cpt} threads)")
     phi0 = inputs.box_draws(C, LO, HI, seed=inputs.SEED_CHAIN_INIT)
     th0 = torch.tensor(inputs.to_natural(phi0), dtype=torch.float64, device=dev)
     ll0, _, _ = p.log_likelihood(th0)
@@ -178,7 +191,7 @@ def main():
                     f"min bulk-ESS = {ess_min:.1f}",
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": "k_solve_resident<128,32,float>",
+                     "kernel": f"k_solve_resident<128,{cpt},float>",
                      "kernel_ms_per_launch": kern_ms / max(launches, 1),
                      "launches": launches},
     }

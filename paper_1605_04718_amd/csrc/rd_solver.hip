@@ -465,10 +465,13 @@ bool tile_supported(int n, int precision, int cpt)
     return tile_kind(n, precision, cpt) != kNone;
 }
 
+// Defaults measured by rd_autotune on MI355X (40-step trial solves): in FP32
+// 16 cells per thread wins at every resident size (64, 256 and 1024-thread
+// workgroups at 32^2, 64^2 and 128^2).
 int default_cpt(int n, int precision)
 {
     if (precision == 0)
-        return n == 32 ? 8 : n == 64 ? 8 : n == 128 ? 32 : n == 256 ? 128 : 0;
+        return n == 32 ? 16 : n == 64 ? 16 : n == 128 ? 16 : n == 256 ? 128 : 0;
     return n == 32 ? 8 : n == 64 ? 16 : n == 128 ? 32 : n == 256 ? 128 : 0;
 }
 
