@@ -69,6 +69,11 @@ __device__ __forceinline__ int uniform(int x)
     return __builtin_amdgcn_readfirstlane(x);
 }
 
+__device__ __forceinline__ float uniform(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
 __device__ __forceinline__ double uniform(double x)
 {
     const uint64_t b = __builtin_bit_cast(uint64_t, x);

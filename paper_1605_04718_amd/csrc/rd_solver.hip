@@ -168,8 +168,7 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
             st = kStBreakdown;
             break;
         }
-        const double alpha = rr / pq;
-        const Real a = (Real)alpha;
+        const Real a = uniform((Real)(rr / pq));
         double rn0 = 0.0, rn1 = 0.0;
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
@@ -187,7 +186,7 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
             st = kStNonfinite;
             break;
         }
-        const Real bt = (Real)(rn / rr);
+        const Real bt = uniform((Real)(rn / rr));
         // x += alpha p_old and p = r + beta p_old (own cells only; the
         // stencil reads of p finished before the p.q barrier).
 #pragma unroll U
@@ -216,10 +215,12 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &eu, Arr &ev, Arr &r, Arr &q, con
                          Real *P, Real *stash, double *red, const Geo<N, R> &g, int &itu,
                          int &itv)
 {
-    const Real inv_dt = (Real)(1.0 / dt);
-    const Real gam = (Real)th[2];
-    const Real src_u = (Real)(th[2] * th[0]);
-    const Real src_v = (Real)(th[2] * th[1]);
+    // Per-item and per-step scalars are wave-uniform; keeping them in SGPRs
+    // leaves the VGPRs to the strip arrays.
+    const Real inv_dt = uniform((Real)(1.0 / dt));
+    const Real gam = uniform((Real)th[2]);
+    const Real src_u = uniform((Real)(th[2] * th[0]));
+    const Real src_v = uniform((Real)(th[2] * th[1]));
     const double n2 = (double)N * (double)N;  // 1/h^2
     // rho_n^-2 = exp(-2 r t_n), t_n = n dt, advanced by the per-class factor
     // exp(-2 r dt) (k_grid_coeffs) each step; relative drift ~n ulp in FP64.
@@ -227,10 +228,10 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &eu, Arr &ev, Arr &r, Arr &q, con
     const double decay = gd.decay;
     double rho_m2 = 1.0;
     int st = 0;
-    for (int s = 0; s < n_steps; ++s, rho_m2 *= decay) {
-        const Real cu = (Real)(rho_m2 * n2);
-        const Real cv = (Real)(th[3] * rho_m2 * n2);
-        const Real dl = (Real)dil;
+    for (int s = 0; s < n_steps; ++s, rho_m2 = uniform(rho_m2 * decay)) {
+        const Real cu = uniform((Real)(rho_m2 * n2));
+        const Real cv = uniform((Real)(th[3] * rho_m2 * n2));
+        const Real dl = uniform((Real)dil);
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
             const Real u = xu[k], v = xv[k];
