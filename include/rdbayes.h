@@ -235,8 +235,11 @@ int32_t surrogate_forward(rd_problem *p, int32_t n, const double *phi, float *ou
 int32_t surrogate_loglik_batch(rd_problem *p, int32_t n, const double *phi, double *phi_sur,
                                void *stream);
 
-/* Copies FP32 master weights / biases of layer `layer` to caller memory
- * (dev float32, [out][in] row-major and [out]) or from it (dir = 1). */
+/* Layer `layer` (0 = input layer) of the surrogate: dir = 0 copies the FP32
+ * master weights [out][in] (row-major) and biases [out] to caller memory
+ * (dev float32), dir = 1 copies them in (and refreshes the BF16 copy),
+ * dir = 2 copies out the weight and bias gradients of the last
+ * surrogate_train_step. */
 int32_t surrogate_params(rd_problem *p, int32_t layer, float *w, float *b, int32_t dir,
                          void *stream);
 

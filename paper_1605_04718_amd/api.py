@@ -168,6 +168,60 @@ class Problem:
                                  _ptr(loglik_prop), _stream(stream)), "accept_batch")
         chains.step = int(c.step)
 
+    # -- surrogate (first stage of delayed acceptance) -------------------
+    def surrogate_create(self, width=512, depth=4, out_side=32, seed=5):
+        check(lib().surrogate_create(self.h, width, depth, out_side, seed), "surrogate_create")
+        self.sur_shape = (width, depth, out_side)
+
+    def downsample(self, u, stream=None):
+        n = u.shape[0]
+        S = self.sur_shape[2]
+        out = torch.empty((n, S * S), dtype=torch.float32, device=u.device)
+        check(lib().downsample_batch(self.h, n, _ptr(u), _ptr(out), _stream(stream)),
+              "downsample_batch")
+        return out
+
+    def surrogate_set_scaling(self, mean, sd, sigma1, stream=None):
+        check(lib().surrogate_set_scaling(self.h, _ptr(mean), _ptr(sd), float(sigma1),
+                                          _stream(stream)), "surrogate_set_scaling")
+
+    def surrogate_train_step(self, phi, target, lr, loss_out=None, stream=None):
+        check(lib().surrogate_train_step(self.h, phi.shape[0], _ptr(phi), _ptr(target), float(lr),
+                                         _ptr(loss_out), _stream(stream)), "surrogate_train_step")
+
+    def surrogate_forward(self, phi, raw=True, stream=None):
+        n = phi.shape[0]
+        S = self.sur_shape[2]
+        out = torch.empty((n, S * S), dtype=torch.float32, device=phi.device)
+        check(lib().surrogate_forward(self.h, n, _ptr(phi), _ptr(out), int(raw), _stream(stream)),
+              "surrogate_forward")
+        return out
+
+    def surrogate_loglik(self, phi, stream=None):
+        out = torch.empty(phi.shape[0], dtype=torch.float64, device=phi.device)
+        check(lib().surrogate_loglik_batch(self.h, phi.shape[0], _ptr(phi), _ptr(out),
+                                           _stream(stream)), "surrogate_loglik_batch")
+        return out
+
+    def surrogate_layer_shapes(self):
+        w, d, S = self.sur_shape
+        sizes = [4] + [w] * d + [S * S]
+        return list(zip(sizes[1:], sizes[:-1]))
+
+    def surrogate_params(self, dir=0, params=None, stream=None):
+        """dir 0: read [(W, b)]; 1: write `params`; 2: read last gradients."""
+        out = []
+        for layer, (fo, fi) in enumerate(self.surrogate_layer_shapes()):
+            if dir == 1:
+                W, b = (t.float().contiguous() for t in params[layer])
+            else:
+                W = torch.empty((fo, fi), dtype=torch.float32, device="cuda")
+                b = torch.empty(fo, dtype=torch.float32, device="cuda")
+            check(lib().surrogate_params(self.h, layer, _ptr(W), _ptr(b), dir, _stream(stream)),
+                  "surrogate_params")
+            out.append((W, b))
+        return out
+
     # -- utilities --------------------------------------------------------
     def autotune(self):
         out = (ctypes.c_int32 * len(self.grids))()

@@ -867,8 +867,8 @@ extern "C" int32_t surrogate_params(rd_problem *p, int32_t layer, float *w, floa
 {
     if (!p || !p->sur)
         return fail(RD_EINVAL, "surrogate_params needs surrogate_create first");
-    if (layer < 0 || layer > surrogate_layers(p->sur) - 1 || (dir != 0 && dir != 1) || !w || !b)
-        return fail(RD_EINVAL, "layer in [0, %d], dir 0/1, w and b required",
+    if (layer < 0 || layer > surrogate_layers(p->sur) - 1 || dir < 0 || dir > 2 || !w || !b)
+        return fail(RD_EINVAL, "layer in [0, %d], dir 0/1/2, w and b required",
                     surrogate_layers(p->sur) - 1);
     HIP_TRY(surrogate_copy_params(p->sur, layer, w, b, dir, (hipStream_t)stream));
     if (dir == 1)

@@ -16,6 +16,10 @@ struct SurrogateDesc {
     int max_batch;
 };
 
+struct SurScale {
+    double lo[4], hi[4];
+};
+
 struct Surrogate;
 
 int32_t surrogate_new(Surrogate **out, const SurrogateDesc &d, uint32_t seed);

@@ -1,0 +1,208 @@
+"""Surrogate MLP (BF16 MFMA kernels) and delayed acceptance vs the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from oracle import sampler as osamp
+from gpu_common import THETA_TRUE, TAU, make_problem, need_gpu, rel_l2
+from paper_1605_04718_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+LO = np.array([0.0, 0.0, math.log(50.0), math.log(5.0)])
+HI = np.array([1.0, 1.0, math.log(500.0), math.log(50.0)])
+
+
+def small_problem(width=128, depth=2, out_side=8, n=32, steps=4, y=True, precision=0, step=None):
+    u0, v0 = inputs.initial_fields(n, 0.1, 0.9)
+    yy, sigma = None, 0.05
+    if y:
+        uo, _, _, _ = oracle.forward_solve(THETA_TRUE, u0, v0, TAU, steps, rtol=1e-12)
+        yy, sigma = inputs.noisy_data(uo, 0.01)
+    p, _, _ = make_problem(n, steps, precision=precision, y=yy, sigma=sigma, u0=u0, v0=v0, lo=LO,
+                           hi=HI, step=step if step is not None else 0.02 * (HI - LO),
+                           max_batch=256)
+    p.surrogate_create(width, depth, out_side, seed=5)
+    return p, u0, v0, yy, sigma
+
+
+def host_params(p, dir=0):
+    return [(W.double().cpu().numpy(), b.double().cpu().numpy()) for W, b in p.surrogate_params(dir)]
+
+
+def test_forward_matches_oracle_with_the_same_weights():
+    import torch
+    need_gpu()
+    p, *_ = small_problem()
+    phi = inputs.box_draws(100, LO, HI, seed=12)  # ragged: padded to 128 rows inside
+    out = p.surrogate_forward(torch.tensor(phi, device="cuda"), raw=True)
+    torch.cuda.synchronize()
+    params = host_params(p)
+    want, _ = omlp.forward(params, omlp.scale_inputs(phi, LO, HI))
+    assert out.shape == (100, 64)
+    # BF16 weights and activations, FP32 accumulation
+    assert rel_l2(out.cpu().numpy(), want) < 3e-2
+    p.close()
+
+
+def test_gradients_loss_and_adam_step_match_oracle():
+    import torch
+    need_gpu()
+    p, *_ = small_problem()
+    rng = np.random.default_rng(3)
+    B = 192
+    phi = inputs.box_draws(B, LO, HI, seed=13)
+    target = rng.standard_normal((B, 64)).astype(np.float32)
+    before = host_params(p)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p.surrogate_train_step(torch.tensor(phi, device="cuda"), torch.tensor(target, device="cuda"),
+                           1e-3, loss)
+    torch.cuda.synchronize()
+    grads = host_params(p, dir=2)
+    after = host_params(p)
+    y, cache = omlp.forward(before, omlp.scale_inputs(phi, LO, HI))
+    want_loss, dy = omlp.mse(y, target.astype(np.float64))
+    want_grads = omlp.backward(before, cache, dy)
+    assert loss.item() == pytest.approx(want_loss, rel=2e-2)
+    for (gW, gb), (wW, wb) in zip(grads, want_grads):
+        assert rel_l2(gW, wW) < 5e-2 and rel_l2(gb, wb) < 5e-2
+    # Adam (FP32 on the GPU) applied to the GPU's own gradients
+    st = {}
+    want_after = omlp.adam_step(before, grads, st, lr=1e-3)
+    for (aW, ab), (wW, wb) in zip(after, want_after):
+        assert np.abs(aW - wW).max() < 2e-6 and np.abs(ab - wb).max() < 2e-6
+    p.close()
+
+
+def test_training_reduces_the_loss_on_a_smooth_target():
+    import torch
+    need_gpu()
+    p, *_ = small_problem(width=512, depth=4, out_side=8)
+    rng = np.random.default_rng(4)
+    B = 256
+    phi_all = inputs.box_draws(2048, LO, HI, seed=14)
+    x = omlp.scale_inputs(phi_all, LO, HI)
+    freq = rng.standard_normal((4, 64))
+    target_all = np.sin(x @ freq).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    losses = []
+    for s in range(200):
+        i = (s * B) % 2048
+        p.surrogate_train_step(torch.tensor(phi_all[i:i + B], device="cuda"),
+                               torch.tensor(target_all[i:i + B], device="cuda"), 1e-3, loss)
+        losses.append(loss.item())
+    torch.cuda.synchronize()
+    assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:5])
+    p.close()
+
+
+def test_downsample_and_surrogate_misfit_match_oracle():
+    import torch
+    need_gpu()
+    p, u0, v0, y, sigma = small_problem()
+    rng = np.random.default_rng(5)
+    u = torch.tensor(rng.standard_normal((3, 32, 32)).astype(np.float32), device="cuda")
+    ds = p.downsample(u)
+    mean = torch.tensor(rng.uniform(0.5, 1.5, 64).astype(np.float32), device="cuda")
+    sd = torch.tensor(rng.uniform(0.1, 0.3, 64).astype(np.float32), device="cuda")
+    p.surrogate_set_scaling(mean, sd, 0.07)
+    phi = inputs.box_draws(10, LO, HI, seed=15)
+    ll = p.surrogate_loglik(torch.tensor(phi, device="cuda"))
+    torch.cuda.synchronize()
+    want_ds = omlp.block_mean(u.double().cpu().numpy(), 8).reshape(3, 64)
+    assert np.allclose(ds.cpu().numpy(), want_ds, rtol=1e-6, atol=1e-6)
+    params = host_params(p)
+    ybar = omlp.block_mean(y, 8).reshape(64)
+    want = omlp.surrogate_misfit(params, phi, LO, HI, mean.double().cpu().numpy(),
+                                 sd.double().cpu().numpy(), ybar, 0.07)
+    assert np.allclose(ll.cpu().numpy(), want, rtol=3e-2)
+    p.close()
+
+
+def test_da_with_constant_surrogate_is_the_plain_chain():
+    """Zero output layer -> Phi~ constant -> stage 1 always accepts and the
+    delayed-acceptance chain equals the plain chain bit for bit."""
+    import torch
+    from paper_1605_04718_amd.api import DA, PLAIN, ChainState
+    need_gpu()
+    step = np.array([0.004, 0.004, 0.01, 0.01])
+    p, u0, v0, y, sigma = small_problem(step=step, precision=1, steps=6)
+    params = p.surrogate_params(0)
+    params[-1] = (torch.zeros_like(params[-1][0]), torch.zeros_like(params[-1][1]))
+    p.surrogate_params(1, params)
+    p.surrogate_set_scaling(torch.ones(64, device="cuda"), torch.ones(64, device="cuda"), 0.1)
+    C, S = 8, 5
+    phi0 = np.tile(inputs.to_sampling(THETA_TRUE)[0], (C, 1))
+    phi0[:, 1] += np.linspace(-0.01, 0.01, C)
+    th0 = torch.tensor(inputs.to_natural(phi0), device="cuda")
+    ll0, _, _ = p.log_likelihood(th0)
+    runs = []
+    for mode in (PLAIN, DA):
+        ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0.clone(), seed=17,
+                               trace_steps=S, da=True)
+        ch.loglik_sur = p.surrogate_loglik(torch.tensor(phi0, device="cuda"))
+        p.mcmc_step(ch, S, mode=mode)
+        torch.cuda.synchronize()
+        runs.append(ch)
+    assert torch.equal(runs[0].trace, runs[1].trace)
+    assert torch.equal(runs[1].n_accept1, runs[1].n_solves)  # stage 1 accepted every in-box proposal
+    p.close()
+
+
+def test_da_step_matches_oracle_decisions():
+    """DA decisions vs the oracle's DA step on the same states, with the
+    oracle evaluating the network in FP64 from the GPU's weights; decisions
+    whose margin is below the BF16 error of Phi~ are not compared."""
+    import torch
+    from paper_1605_04718_amd.api import DA, ChainState
+    need_gpu()
+    step = np.array([0.01, 0.01, 0.02, 0.02])
+    p, u0, v0, y, sigma = small_problem(step=step, precision=1, steps=6)
+    p.surrogate_set_scaling(torch.full((64,), 1.0, device="cuda"),
+                            torch.full((64,), 0.05, device="cuda"), 0.2)
+    C = 64
+    phi0 = np.tile(inputs.to_sampling(THETA_TRUE)[0], (C, 1))
+    phi0[:, 0] += np.linspace(-0.02, 0.02, C)
+    th0 = torch.tensor(inputs.to_natural(phi0), device="cuda")
+    ll0, _, _ = p.log_likelihood(th0)
+    ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0.clone(), seed=23, da=True)
+    ch.loglik_sur = p.surrogate_loglik(torch.tensor(phi0, device="cuda"))
+    lls0 = ch.loglik_sur.cpu().numpy().copy()
+    p.mcmc_step(ch, 1, mode=DA)
+    torch.cuda.synchronize()
+    params = host_params(p)
+    ybar = omlp.block_mean(y, 8).reshape(64)
+
+    def sur(q):
+        return float(omlp.surrogate_misfit(params, q, LO, HI, np.ones(64), np.full(64, 0.05), ybar,
+                                           0.2)[0])
+
+    def ll(q):
+        return float(oracle.loglik_batch(inputs.to_natural(q), u0, v0, y, sigma, TAU, 6,
+                                         rtol=1e-12)[0][0])
+
+    got_phi = ch.phi.cpu().numpy()
+    acc1 = ch.n_accept1.cpu().numpy()
+    compared = 0
+    for c in range(C):
+        prop = osamp.propose(phi0[c], 23, c, 0, step, 0b1111)
+        if not osamp.in_box(prop, LO, HI):
+            continue
+        s0, s1 = sur(phi0[c]), sur(prop)
+        tol = 0.05 * (abs(s0) + abs(s1) + 1.0)  # BF16 error bound of Phi~ differences
+        if abs(math.log(oracle.uniform1(23, c, 0, osamp.PURPOSE_STAGE1)) - (s0 - s1)) < tol:
+            continue
+        if math.log(oracle.uniform1(23, c, 0, osamp.PURPOSE_STAGE1)) < s0 - s1:
+            la2 = (ll0[c].item() - ll(prop)) - (s0 - s1)
+            if abs(math.log(oracle.uniform1(23, c, 0, osamp.PURPOSE_ACCEPT)) - la2) < tol:
+                continue
+        res = osamp.da_step(phi0[c], ll0[c].item(), lls0[c], 23, c, 0, LO, HI, step, 0b1111, ll, sur)
+        assert bool(acc1[c]) == res[3]
+        if res[3]:
+            assert np.allclose(got_phi[c], res[0], rtol=1e-12, atol=1e-13)
+        compared += 1
+    assert compared > C // 2
+    p.close()
