@@ -83,7 +83,8 @@ struct rd_problem {
     int *status_ws = nullptr;
     int *iters_ws = nullptr;
     uint64_t *ctr = nullptr;
-    void *gws = nullptr;
+    void *gws = nullptr;     // per-workgroup solve slots
+    size_t gws_stride = 0;
     int gws_slots = 0;
     // timing of the fused solve kernel
     bool timing = false;
@@ -117,13 +118,16 @@ int32_t upload_field(rd_problem *p, const double *host, int nn, void **out)
 {
     int32_t err = RD_OK;
     if (p->desc.precision == RD_PRECISION_FP32) {
-        std::vector<float> f(nn);
-        for (int k = 0; k < nn; ++k)
+        // [hi | lo]: the FP32 solver carries fields as unevaluated sums
+        std::vector<float> f(2 * nn);
+        for (int k = 0; k < nn; ++k) {
             f[k] = (float)host[k];
-        *out = dmalloc(p, sizeof(float) * nn, &err);
+            f[nn + k] = (float)(host[k] - (double)f[k]);
+        }
+        *out = dmalloc(p, sizeof(float) * 2 * nn, &err);
         if (!*out)
             return err;
-        HIP_TRY(hipMemcpy(*out, f.data(), sizeof(float) * nn, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(*out, f.data(), sizeof(float) * 2 * nn, hipMemcpyHostToDevice));
     } else {
         *out = dmalloc(p, sizeof(double) * nn, &err);
         if (!*out)
@@ -201,6 +205,7 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     a.v_out = v_out;
     a.queue = p->queue;
     a.gws = p->gws;
+    a.gws_stride = p->gws_stride;
     a.gws_slots = p->gws_slots;
     const TileChoice t = p->tile[g];
     // wgs_per_cu was queried when the tile was chosen: no runtime query may
@@ -410,26 +415,27 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         destroy_problem(p);
         return fail(RD_EHIP, "upload of grid table failed");
     }
-    // Streamed workspace: one slot per resident workgroup of the largest
-    // streamed class.
+    // Solve workspace: one slot per resident workgroup, sized for every tile
+    // the autotuner may pick (the predictor history, 2 n^2 values, and for
+    // streamed tiles the 7 strip arrays as well).
     size_t slot = 0;
     int slots = 0;
     for (int g = 0; g < desc->n_grids; ++g) {
         const int n = p->grids_host[g].n;
-        for (int cpt : {16, 32, 64, 128}) {
-            if (tile_streamed(n, desc->precision, cpt)) {
-                slot = std::max(slot, streamed_slot_bytes(n, desc->precision));
+        for (int cpt : {4, 8, 16, 32, 64, 128}) {
+            if (tile_supported(n, desc->precision, cpt)) {
+                slot = std::max(slot, solve_slot_bytes(n, desc->precision, cpt));
                 slots = std::max(slots, p->n_cu * solve_wgs_per_cu(n, desc->precision, cpt));
             }
         }
     }
-    if (slots > 0) {
-        p->gws = dmalloc(p, slot * slots, &err);
-        p->gws_slots = slots;
-        if (err != RD_OK) {
-            destroy_problem(p);
-            return err;
-        }
+    slot = (slot + 255) / 256 * 256;
+    p->gws = dmalloc(p, slot * (size_t)slots, &err);
+    p->gws_stride = slot;
+    p->gws_slots = slots;
+    if (err != RD_OK) {
+        destroy_problem(p);
+        return err;
     }
     *out = p;
     return RD_OK;

@@ -148,6 +148,30 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *slot)
     b = uniform(sb);
 }
 
+template <int kWaves, int M>
+__device__ __forceinline__ void block_sum_n(double (&v)[M], double *slot)
+{
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        v[m] = wave_sum_last_lane(v[m]);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    if (lane == kLastLane) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            slot[m * kWaves + wid] = v[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+            s += slot[m * kWaves + w];
+        v[m] = uniform(s);
+    }
+}
+
 __device__ __forceinline__ bool finite(double x)
 {
     return __builtin_isfinite(x);

@@ -12,8 +12,9 @@ struct GridDev {
     int n;             // cells per side
     int growth;        // 0 stationary, 1 rho = exp(rate t)
     double rate;       // growth rate r
-    const void *u0;    // [n*n] initial u in the problem precision
-    const void *v0;    // [n*n] initial v
+    const void *u0;    // initial u in the problem precision: FP64 [n*n]; FP32
+                       // [2][n*n], rounded value then the rounding remainder
+    const void *v0;    // initial v, same layout
     const double *y;   // [n*n] data (float64) or null
     double inv_2s2;    // 1 / (2 sigma^2)
     double cost;       // relative cost of one solve (for queue ordering)
@@ -39,8 +40,10 @@ struct SolveArgs {
     void *u_out;             // [n][N*N] final u (null: skip)
     void *v_out;             // [n][N*N] final v (null: skip)
     unsigned *queue;         // work-queue head (zeroed before the launch)
-    void *gws;               // global workspace for the streamed (n = 256) variant
-    int gws_slots;           // number of per-workgroup slots in gws
+    void *gws;               // per-workgroup workspace slots (predictor history,
+                             // streamed strip arrays)
+    size_t gws_stride;       // bytes per slot
+    int gws_slots;           // number of slots
 };
 
 // Solver tile choices: cells per thread (rows of the strip a thread owns).
@@ -57,7 +60,7 @@ bool tile_supported(int n, int precision, int cpt);
 bool tile_streamed(int n, int precision, int cpt);
 int solve_wgs_per_cu(int n, int precision, int cpt);
 int default_cpt(int n, int precision);
-size_t streamed_slot_bytes(int n, int precision);
+size_t solve_slot_bytes(int n, int precision, int cpt);
 hipError_t launch_fill_u32(unsigned *p, unsigned v, int count, hipStream_t s);
 hipError_t launch_grid_coeffs(GridDev *grids, int n_grids, double dt, hipStream_t s);
 

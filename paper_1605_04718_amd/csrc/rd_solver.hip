@@ -44,6 +44,15 @@ struct Geo {
         ie = i < N - 1 ? i + 1 : i;  // mirror ghost at x = 1
     }
     __device__ int idx(int k) const { return (j0 + k) * N + i; }
+    // Own-cell offset for global-memory accesses, made opaque at each use:
+    // otherwise the compiler hoists the R per-cell 64-bit addresses of every
+    // global array out of the time loop and keeps them all live.
+    __device__ __forceinline__ int off() const
+    {
+        int o = j0 * N + i;
+        asm volatile("" : "+v"(o));
+        return o;
+    }
 };
 
 // Memory-motion fence every kGroup cells of an unrolled strip loop: without
@@ -59,10 +68,25 @@ constexpr int kGroup = 4;
         __builtin_amdgcn_sched_barrier(0);                  \
     }
 
+// Pins a value in a register at this point of the program: the empty
+// volatile asm keeps its order with the group fences, so the arithmetic that
+// produces the value cannot sink below the next fence.  Without it the
+// compiler hoists the LDS reads of a whole strip above the arithmetic of the
+// first cells and keeps them all live.
+#define RD_PIN(x) asm volatile("" : "+v"(x))
+
 template <typename Real, int R>
 struct RegArr {
     Real v[R];
     __device__ __forceinline__ Real &operator[](int k) { return v[k]; }
+    __device__ __forceinline__ Real operator[](int k) const { return v[k]; }
+};
+
+// Strip view of an N*N array in LDS (k-th own cell at base[k*N]).
+template <typename Real, int N>
+struct LdsArr {
+    Real *base;
+    __device__ __forceinline__ Real &operator[](int k) const { return base[k * N]; }
 };
 
 // Strip view of an N*N array in global memory (k-th own cell at base[k*N]).
@@ -93,48 +117,167 @@ __device__ __forceinline__ void sweep(const Real *P, const Geo<N, R> &g, F &&f)
     }
 }
 
-// LDS reduction slots: [0, 2W) setup pair, [2W, 3W) p.q, [3W, 4W) r.r,
-// [4W, 5W) misfit.
+// P <- own cells of a global array (src = own-cell pointer, cell k at
+// src[k N]).  kLds: P is in LDS (resident variant).  When the 64 lanes of a wave own 64 consecutive words of every
+// strip row (N >= 64) the copy uses direct global->LDS loads, which need no
+// VGPRs and keep all R loads in flight at once; otherwise it goes through
+// registers.  The caller places a barrier before the stencil reads P.
+template <int N, int R, int U, bool kLds, typename Real>
+__device__ __forceinline__ void copy_to_lds(const Real *src, Real *P, const Geo<N, R> &g)
+{
+    if constexpr (kLds && N >= kWave && sizeof(Real) == 4) {
+        const int row0 = uniform(g.j0 * N + (g.i & ~(kWave - 1)));
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            __builtin_amdgcn_global_load_lds(src + k * N, P + row0 + k * N, 4, 0, 0);
+        __builtin_amdgcn_s_waitcnt(0);  // the LDS writes have landed
+    } else {
+#pragma unroll U
+        for (int k = 0; k < R; ++k)
+            P[g.idx(k)] = src[k * N];
+    }
+}
+
+// LDS reduction slots: [0, 4W) set-up, [4W, 5W) p.q, [5W, 6W) r.r,
+// [6W, 7W) misfit.
 template <int NW>
 struct Slots {
-    static constexpr int setup = 0, pq = 2 * NW, rr = 3 * NW, misfit = 4 * NW, total = 5 * NW;
+    static constexpr int setup = 0, pq = 4 * NW, rr = 5 * NW, misfit = 6 * NW, total = 7 * NW;
 };
 
-// CG for (1/dt + e) x - c' Lap_h x = x_old/dt + src, from x = x_old.
-// On entry `es` holds e (reaction + dilution part of the diagonal); on exit
-// it holds sigma = 1/dt + e.  r and q are scratch.  Returns RD status bits.
-template <int N, int R, int U, int NW, typename Real, class Arr>
-__device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Real src,
-                        double rtol2, int maxit, Real *P, double *red, const Geo<N, R> &g,
+// In FP32 a field is carried as an unevaluated sum hi + lo (|lo| <= ulp(hi)/2):
+// the residual of an FP32-rounded field alone has a floor of about
+// 2^-24 (1/dt + 8 c' n^2) |x| from the rounding noise, which for the stiff
+// v system lies far above any useful CG tolerance, and CG would spend its
+// iterations on that noise.  With the low part the residual is exact to
+// FP32 rounding of its own terms, CG solves for the increment of the step
+// (a small quantity, well represented in FP32), and the increment is folded
+// back into hi + lo without loss.
+template <typename Real>
+struct Compensated {
+    static constexpr bool on = sizeof(Real) == 4;
+};
+
+// Error-free sum (Knuth's TwoSum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bv = s - a;
+    e = (a - (s - bv)) + (b - bv);
+}
+
+// CG for the increment d of one implicit step of species kSp (0: u, 1: v),
+//   (1/dt + e) x' - c' Lap_h x' = x/dt + src,  x' = x + d,
+// where x = hi (+ lo in FP32, global memory, this item's slot), and e, the
+// reaction + dilution part of the diagonal, is formed at each use from the
+// level-n fields: e_u = 2r + g (1 - u v), e_v = 2r + g u^2, with S the other
+// species' field (v^n for u, u^n for v).  Not storing the diagonal keeps
+// one strip array fewer in VGPRs.  hi is not changed (the caller folds d
+// in).  r and q are scratch.  Returns RD status bits.
+//
+// H (global, the previous step's increment, or null): with `pred`, CG starts
+// from one minimal-residual step along it, d0 = w H with
+// w = (r0, A H) / (A H, A H), which can only lower the residual.  When the
+// trajectory is smooth in time this removes the part of r0 that the last
+// step predicts.  The system and the stopping test are unchanged:
+// |r| <= rtol |b| on the recursively updated residual.
+template <int N, int R, int U, int NW, bool kLds, int kSp, typename Real, class Arr, class SArr>
+__device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Real inv_dt, Real c,
+                        Real src, Real dl, Real gam, double rtol2, int maxit, Real *P,
+                        const Real *lo, const Real *H, bool pred, double *red, const Geo<N, R> &g,
                         int &it_acc)
 {
+    constexpr bool comp = Compensated<Real>::on;
+    // e(k) and sigma(k) = 1/dt + e(k)
+    const Real e0 = uniform(kSp == 0 ? dl + gam : dl);
+    const Real s0 = uniform(e0 + inv_dt);
+    auto e_at = [&](int k) -> Real {
+        if constexpr (kSp == 0)
+            return e0 - gam * (hi[k] * S[k]);
+        else
+            return e0 + gam * (S[k] * S[k]);
+    };
+    auto sigma_at = [&](int k) -> Real {
+        if constexpr (kSp == 0)
+            return s0 - gam * (hi[k] * S[k]);
+        else
+            return s0 + gam * (S[k] * S[k]);
+    };
 #pragma unroll U
     for (int k = 0; k < R; ++k) {
-        P[g.idx(k)] = x[k];
+        P[g.idx(k)] = hi[k];
         RD_GROUP_FENCE(k)
     }
     __syncthreads();
 
-    // r0 = b - A x0 = src - e x0 - c t(x0): the 1/dt terms cancel exactly,
-    // so r0 (the scaled time derivative) keeps full relative precision.
-    // Two interleaved FP64 partial sums per dot product halve the dependent
-    // accumulation chains.
-    double bb0 = 0.0, bb1 = 0.0, rr0 = 0.0, rr1 = 0.0;
+    // r0 = b - A x = src - e x - c t(x): the 1/dt terms cancel exactly, so
+    // r0 (the scaled time derivative) keeps full relative precision.
+    double bb = 0.0, rr = 0.0;
     sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
         const Real b = own * inv_dt + src;
-        const Real res = src - es[k] * own - c * t;
+        Real res = src - e_at(k) * own - c * t;
+        RD_PIN(res);
         r[k] = res;
-        es[k] = es[k] + inv_dt;
-        if (k & 1) {
-            bb1 += (double)b * (double)b;
-            rr1 += (double)res * (double)res;
-        } else {
-            bb0 += (double)b * (double)b;
-            rr0 += (double)res * (double)res;
+        bb += (double)b * (double)b;
+        RD_PIN(bb);
+        if constexpr (!comp) {
+            rr += (double)res * (double)res;
+            RD_PIN(rr);
         }
     });
-    double bb = bb0 + bb1, rr = rr0 + rr1;
-    block_sum2<NW>(bb, rr, red + Slots<NW>::setup);
+    if constexpr (comp) {
+        // the low part's share of A x
+        __syncthreads();
+        copy_to_lds<N, R, U, kLds>(lo + g.off(), P, g);
+        __syncthreads();
+        sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
+            Real res = r[k] - (e_at(k) * own + c * t);
+            RD_PIN(res);
+            r[k] = res;
+            rr += (double)res * (double)res;
+            RD_PIN(rr);
+        });
+    }
+    if (H && pred) {
+        __syncthreads();  // every stencil read of P is done
+        copy_to_lds<N, R, U, kLds>(H + g.off(), P, g);
+        __syncthreads();
+        double rw = 0.0, ww = 0.0;
+        sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
+            Real w = c * t + sigma_at(k) * own;  // (A H) at the cell
+            RD_PIN(w);
+            q[k] = w;
+            rw += (double)r[k] * (double)w;
+            ww += (double)w * (double)w;
+            RD_PIN(rw);
+            RD_PIN(ww);
+        });
+        double v4[4] = {bb, rr, rw, ww};
+        block_sum_n<NW>(v4, red + Slots<NW>::setup);
+        bb = v4[0];
+        rr = v4[1];
+        rw = v4[2];
+        ww = v4[3];
+        const Real w = uniform((Real)((ww > 0.0 && finite(rw)) ? rw / ww : 0.0));
+#pragma unroll U
+        for (int k = 0; k < R; ++k) {
+            d[k] = w * P[g.idx(k)];
+            r[k] = r[k] - w * q[k];
+            RD_GROUP_FENCE(k)
+        }
+        // |r0 - w A H|^2 expanded with the rounded w (the elementwise
+        // rounding of r adds a relative 2^-24 per cell at most).
+        const double wd = (double)w;
+        const double rn = rr - 2.0 * wd * rw + wd * wd * ww;
+        rr = uniform(rn > 0.0 ? rn : 0.0);
+    } else {
+        block_sum2<NW>(bb, rr, red + Slots<NW>::setup);
+#pragma unroll U
+        for (int k = 0; k < R; ++k)
+            d[k] = Real(0);
+    }
+    // The reduction barrier above also ends every stencil read of P, and each
+    // thread now only rewrites its own cells.
 #pragma unroll U
     for (int k = 0; k < R; ++k) {
         P[g.idx(k)] = r[k];
@@ -150,14 +293,20 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
             break;
         }
         __syncthreads();  // p visible to the neighbours
+        // Two interleaved FP64 partial sums per dot product halve the
+        // dependent accumulation chains.
         double pq0 = 0.0, pq1 = 0.0;
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
-            const Real qq = c * t + es[k] * own;
+            Real qq = c * t + sigma_at(k) * own;
+            RD_PIN(qq);
             q[k] = qq;
-            if (k & 1)
+            if (k & 1) {
                 pq1 += (double)own * (double)qq;
-            else
+                RD_PIN(pq1);
+            } else {
                 pq0 += (double)own * (double)qq;
+                RD_PIN(pq0);
+            }
         });
         const double pq = block_sum<NW>(pq0 + pq1, red + Slots<NW>::pq);
         if (!finite(pq)) {
@@ -187,12 +336,12 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
             break;
         }
         const Real bt = uniform((Real)(rn / rr));
-        // x += alpha p_old and p = r + beta p_old (own cells only; the
+        // d += alpha p_old and p = r + beta p_old (own cells only; the
         // stencil reads of p finished before the p.q barrier).
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
             const Real p = P[g.idx(k)];
-            x[k] = x[k] + a * p;
+            d[k] = d[k] + a * p;
             P[g.idx(k)] = r[k] + bt * p;
             RD_GROUP_FENCE(k)
         }
@@ -203,65 +352,151 @@ __device__ int cg_solve(Arr &x, Arr &es, Arr &r, Arr &q, Real inv_dt, Real c, Re
     return st;
 }
 
+// x' = x + d: hi (+ lo) absorb the increment.  kDGlobal: d is read from the
+// global array H (own-cell layout); otherwise d is in registers and is also
+// recorded in H (when non-null) for the next step's predictor.
+template <int N, int R, int U, bool kDGlobal, typename Real, class Arr>
+__device__ __forceinline__ void fold(Arr &hi, Arr &d, Real *lo, Real *H, const Geo<N, R> &g)
+{
+    const int o = g.off();
+#pragma unroll U
+    for (int k = 0; k < R; ++k) {
+        const Real dk = kDGlobal ? H[o + k * N] : d[k];
+        if constexpr (Compensated<Real>::on) {
+            float s, e;
+            two_sum(hi[k], dk, s, e);
+            const float l = lo[o + k * N] + e;
+            const float nh = s + l;
+            hi[k] = nh;
+            lo[o + k * N] = l - (nh - s);
+        } else {
+            hi[k] = hi[k] + dk;
+        }
+        if (!kDGlobal && H)
+            H[o + k * N] = dk;
+    }
+}
+
+// d -> H (own cells).
+template <int N, int R, int U, typename Real, class Arr>
+__device__ __forceinline__ void store_increment(Arr &d, Real *H, const Geo<N, R> &g)
+{
+    const int o = g.off();
+#pragma unroll U
+    for (int k = 0; k < R; ++k)
+        H[o + k * N] = d[k];
+}
+
+// Per-workgroup global slot of the solve: the low parts of u and v (FP32),
+// the last increments of u and v (predictor), then (streamed variant only)
+// the strip arrays and p.
+template <typename Real>
+struct SlotLayout {
+    static constexpr int lo_u = 0, lo_v = 1, h_u = 2, h_v = 3, arrays = 4;
+};
+
 // All IMEX steps of one item (Sec. 3.1.1):
 //   (1/dt + 2 r_n + g (1 - u v)) u' - rho_n^-2 Lap u' = u/dt + g a
 //   (1/dt + 2 r_n + g u^2)       v' - d rho_n^-2 Lap v' = v/dt + g b
-// `stash` (LDS, N*N, resident variant only; null otherwise) parks v during
-// the u solve, where it is not used, so that the u solve keeps only five
-// strip arrays in VGPRs.
-template <int N, int R, int U, int NW, typename Real, class Arr>
-__device__ int integrate(Arr &xu, Arr &xv, Arr &eu, Arr &ev, Arr &r, Arr &q, const double th[4],
+// Both systems use the fields of level n only, so they are solved one after
+// the other with one set of CG work arrays (r, q, d); u is advanced only
+// after the v solve, which needs u^n.  Resident variant (kLds): P and
+// `stash` are in LDS and the stash parks the field not being solved for
+// (v^n during the u solve, u^n during the v solve), so that a solve keeps
+// four strip arrays in VGPRs.  Streamed variant: all arrays are global and
+// `stash` is null.  `slot` is the item's global slot (SlotLayout).
+template <int N, int R, int U, int NW, bool kLds, typename Real, class Arr>
+__device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double th[4],
                          const GridDev &gd, double dt, int n_steps, double rtol2, int maxit,
-                         Real *P, Real *stash, double *red, const Geo<N, R> &g, int &itu,
-                         int &itv)
+                         Real *P, Real *stash, Real *slot, double *red, const Geo<N, R> &g,
+                         int &itu, int &itv)
 {
+    using L = SlotLayout<Real>;
+    constexpr bool comp = Compensated<Real>::on;
+    Real *const lo_u = comp ? slot + L::lo_u * N * N : nullptr;
+    Real *const lo_v = comp ? slot + L::lo_v * N * N : nullptr;
+    Real *const h_u = slot + L::h_u * N * N;
+    Real *const h_v = slot + L::h_v * N * N;
     // Per-item and per-step scalars are wave-uniform; keeping them in SGPRs
     // leaves the VGPRs to the strip arrays.
     const Real inv_dt = uniform((Real)(1.0 / dt));
     const Real gam = uniform((Real)th[2]);
     const Real src_u = uniform((Real)(th[2] * th[0]));
     const Real src_v = uniform((Real)(th[2] * th[1]));
+    const Real dl = uniform((Real)gd.dil);  // m rho'/rho with m = 2
     const double n2 = (double)N * (double)N;  // 1/h^2
     // rho_n^-2 = exp(-2 r t_n), t_n = n dt, advanced by the per-class factor
     // exp(-2 r dt) (k_grid_coeffs) each step; relative drift ~n ulp in FP64.
-    const double dil = gd.dil;  // m rho'/rho with m = 2
     const double decay = gd.decay;
     double rho_m2 = 1.0;
     int st = 0;
     for (int s = 0; s < n_steps; ++s, rho_m2 = uniform(rho_m2 * decay)) {
         const Real cu = uniform((Real)(rho_m2 * n2));
         const Real cv = uniform((Real)(th[3] * rho_m2 * n2));
-        const Real dl = uniform((Real)dil);
-#pragma unroll U
-        for (int k = 0; k < R; ++k) {
-            const Real u = xu[k], v = xv[k];
-            eu[k] = dl + gam * (Real(1) - u * v);
-            ev[k] = dl + gam * (u * u);
-        }
-        if (stash) {
+        if constexpr (kLds) {
+            LdsArr<Real, N> sv{stash + g.idx(0)};
 #pragma unroll U
             for (int k = 0; k < R; ++k)
-                stash[g.idx(k)] = xv[k];
-        }
-        st = cg_solve<N, R, U, NW>(xu, eu, r, q, inv_dt, cu, src_u, rtol2, maxit, P, red, g, itu);
-        if (stash) {
+                sv[k] = xv[k];
+            st = cg_solve<N, R, U, NW, kLds, 0>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
+                                                maxit, P, lo_u, h_u, s > 0, red, g, itu);
+#pragma unroll U
+            for (int k = 0; k < R; ++k) {
+                xv[k] = sv[k];
+                if (!st)
+                    sv[k] = xu[k];
+            }
+            if (st)
+                break;
+            store_increment<N, R, U>(d, h_u, g);
+            st = cg_solve<N, R, U, NW, kLds, 1>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
+                                                maxit, P, lo_v, h_v, s > 0, red, g, itv);
 #pragma unroll U
             for (int k = 0; k < R; ++k)
-                xv[k] = stash[g.idx(k)];
+                xu[k] = sv[k];
+        } else {
+            st = cg_solve<N, R, U, NW, kLds, 0>(xu, xv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
+                                                maxit, P, lo_u, h_u, s > 0, red, g, itu);
+            if (st)
+                break;
+            store_increment<N, R, U>(d, h_u, g);
+            st = cg_solve<N, R, U, NW, kLds, 1>(xv, xu, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
+                                                maxit, P, lo_v, h_v, s > 0, red, g, itv);
         }
         if (st)
             break;
-        st = cg_solve<N, R, U, NW>(xv, ev, r, q, inv_dt, cv, src_v, rtol2, maxit, P, red, g, itv);
-        if (st)
-            break;
+        fold<N, R, U, false>(xv, d, lo_v, h_v, g);
+        fold<N, R, U, true>(xu, d, lo_u, h_u, g);
     }
     return st;
 }
 
+// Item start: hi in registers (or the streamed arrays), lo in the slot.
+template <int N, int R, int U, typename Real, class Arr>
+__device__ __forceinline__ void load_initial(const GridDev &gd, Arr &xu, Arr &xv, Real *slot,
+                                             const Geo<N, R> &g)
+{
+    using L = SlotLayout<Real>;
+    const int o = g.off();
+    const Real *u0 = (const Real *)gd.u0 + o;
+    const Real *v0 = (const Real *)gd.v0 + o;
+#pragma unroll U
+    for (int k = 0; k < R; ++k) {
+        xu[k] = u0[k * N];
+        xv[k] = v0[k * N];
+        if constexpr (Compensated<Real>::on) {
+            // the FP32 initial fields are stored as [hi | lo]
+            slot[L::lo_u * N * N + o + k * N] = u0[N * N + k * N];
+            slot[L::lo_v * N * N + o + k * N] = v0[N * N + k * N];
+        }
+    }
+}
+
 template <int N, int R, typename Real, class Arr>
 __device__ void finish_item(const SolveArgs &a, const GridDev &gd, int c, Arr &xu, Arr &xv, int st,
-                            int itu, int itv, const Geo<N, R> &g, double *red)
+                            int itu, int itv, const Real *slot, const Geo<N, R> &g, double *red)
 {
+    using L = SlotLayout<Real>;
     constexpr int NW = (N * N / R) / kWave;
     constexpr int U = (R <= 32) ? R : 4;
     const size_t off = (size_t)c * N * N;
@@ -278,9 +513,13 @@ __device__ void finish_item(const SolveArgs &a, const GridDev &gd, int c, Arr &x
     if (a.phi) {
         double s = 0.0;
         if (gd.y) {
+            const int o = g.off();
 #pragma unroll U
             for (int k = 0; k < R; ++k) {
-                const double e = gd.y[g.idx(k)] - (double)xu[k];
+                double u = (double)xu[k];
+                if constexpr (Compensated<Real>::on)
+                    u += (double)slot[L::lo_u * N * N + o + k * N];
+                const double e = gd.y[o + k * N] - u;
                 s += e * e;
             }
         }
@@ -318,6 +557,7 @@ __global__ __launch_bounds__(N *N / R) void k_solve_resident(SolveArgs a)
     __shared__ double red[Slots<NW>::total];
     __shared__ int s_item;
     const Geo<N, R> g;
+    Real *slot = (Real *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
     for (int item = next_item(a.queue, &s_item); item < a.n_items;
          item = next_item(a.queue, &s_item)) {
         const int c = uniform(a.order ? a.order[item] : item);
@@ -325,37 +565,34 @@ __global__ __launch_bounds__(N *N / R) void k_solve_resident(SolveArgs a)
             const GridDev &gd = a.grids[uniform(a.grid_id ? a.grid_id[c] : 0)];
             const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
                                   a.theta[4 * c + 3]};
-            RegArr<Real, R> xu, xv, eu, ev, r, q;
-            const Real *u0 = (const Real *)gd.u0;
-            const Real *v0 = (const Real *)gd.v0;
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                xu[k] = u0[g.idx(k)];
-                xv[k] = v0[g.idx(k)];
-            }
+            RegArr<Real, R> xu, xv, r, q, d;
+            load_initial<N, R, R>(gd, xu, xv, slot, g);
             int itu = 0, itv = 0;
-            const int st = integrate<N, R, R, NW>(xu, xv, eu, ev, r, q, th, gd, a.dt, a.n_steps,
-                                                  a.rtol2, a.maxit, P, stash, red, g, itu, itv);
-            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, g, red);
+            const int st = integrate<N, R, R, NW, true>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps,
+                                                  a.rtol2, a.maxit, P, stash, slot, red, g, itu,
+                                                  itv);
+            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
         }
     }
 }
 
-// Streamed variant: strip arrays and p in a global slot of 7 N*N arrays.
+// Streamed variant: the strip arrays and p follow the SlotLayout arrays in
+// the workgroup's global slot.
 template <int N, int R, typename Real>
 __global__ __launch_bounds__(N *N / R) void k_solve_streamed(SolveArgs a)
 {
     constexpr int NW = (N * N / R) / kWave;
     constexpr int U = 4;
+    constexpr size_t NN = (size_t)N * N;
     __shared__ double red[Slots<NW>::total];
     __shared__ int s_item;
     const Geo<N, R> g;
-    Real *slot = (Real *)a.gws + (size_t)blockIdx.x * 7 * N * N;
-    Real *P = slot + 6 * (size_t)N * N;
+    Real *slot = (Real *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
+    Real *arr = slot + SlotLayout<Real>::arrays * NN;
+    Real *P = arr + 5 * NN;
     const int base = g.j0 * N + g.i;
-    GlobArr<Real, N> xu{slot + base}, xv{slot + (size_t)N * N + base},
-        eu{slot + 2 * (size_t)N * N + base}, ev{slot + 3 * (size_t)N * N + base},
-        r{slot + 4 * (size_t)N * N + base}, q{slot + 5 * (size_t)N * N + base};
+    GlobArr<Real, N> xu{arr + base}, xv{arr + NN + base}, r{arr + 2 * NN + base},
+        q{arr + 3 * NN + base}, d{arr + 4 * NN + base};
     for (int item = next_item(a.queue, &s_item); item < a.n_items;
          item = next_item(a.queue, &s_item)) {
         const int c = uniform(a.order ? a.order[item] : item);
@@ -363,18 +600,12 @@ __global__ __launch_bounds__(N *N / R) void k_solve_streamed(SolveArgs a)
             const GridDev &gd = a.grids[uniform(a.grid_id ? a.grid_id[c] : 0)];
             const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
                                   a.theta[4 * c + 3]};
-            const Real *u0 = (const Real *)gd.u0;
-            const Real *v0 = (const Real *)gd.v0;
-#pragma unroll U
-            for (int k = 0; k < R; ++k) {
-                xu[k] = u0[g.idx(k)];
-                xv[k] = v0[g.idx(k)];
-            }
+            load_initial<N, R, U>(gd, xu, xv, slot, g);
             int itu = 0, itv = 0;
-            const int st = integrate<N, R, U, NW>(xu, xv, eu, ev, r, q, th, gd, a.dt, a.n_steps,
-                                                  a.rtol2, a.maxit, P, (Real *)nullptr, red, g,
-                                                  itu, itv);
-            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, g, red);
+            const int st = integrate<N, R, U, NW, false>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps,
+                                                  a.rtol2, a.maxit, P, (Real *)nullptr, slot, red,
+                                                  g, itu, itv);
+            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
         }
     }
 }
@@ -453,8 +684,6 @@ hipError_t go_resident(const SolveArgs &a, int wgs, hipStream_t s)
 template <int N, int R, typename Real>
 hipError_t go_streamed(const SolveArgs &a, int wgs, hipStream_t s)
 {
-    if (wgs > a.gws_slots)
-        wgs = a.gws_slots;
     hipLaunchKernelGGL((k_solve_streamed<N, R, Real>), dim3(wgs), dim3(N * N / R), 0, s, a);
     return hipGetLastError();
 }
@@ -476,9 +705,10 @@ int default_cpt(int n, int precision)
     return n == 32 ? 8 : n == 64 ? 16 : n == 128 ? 32 : n == 256 ? 128 : 0;
 }
 
-size_t streamed_slot_bytes(int n, int precision)
+size_t solve_slot_bytes(int n, int precision, int cpt)
 {
-    return (size_t)7 * n * n * (precision ? sizeof(double) : sizeof(float));
+    const size_t arrays = tile_kind(n, precision, cpt) == kStreamed ? 10 : 4;
+    return arrays * n * n * (precision ? sizeof(double) : sizeof(float));
 }
 
 template <typename K>
@@ -523,6 +753,10 @@ hipError_t launch_solve(int n, int precision, TileChoice tile, const SolveArgs &
                         hipStream_t s)
 {
     const int cpt = tile.cpt;
+    // Every workgroup owns one workspace slot (predictor history; streamed
+    // tiles also keep their strip arrays there).
+    if (!a.gws || wgs > a.gws_slots || a.gws_stride < solve_slot_bytes(n, precision, cpt))
+        return hipErrorInvalidValue;
 #define RD_RES(NN, RR, T)                                     \
     if (n == NN && cpt == RR)                                 \
         return go_resident<NN, RR, T>(a, wgs, s);

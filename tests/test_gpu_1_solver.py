@@ -37,8 +37,10 @@ def test_fp64_resident_matches_oracle(n, steps):
     for k, (uo, vo, ito, sto) in enumerate(oracle_fields(thetas, u0, v0, steps)):
         assert st[k] == 0 and sto == 0
         assert rel_l2(ug[k], uo) < 1e-10 and rel_l2(vg[k], vo) < 1e-10, (k, rel_l2(ug[k], uo))
-        # same algorithm: iteration counts agree up to one per solve
-        assert np.all(np.abs(it[k] - ito) <= steps)
+        # CG on the same systems; the GPU starts each solve from the
+        # minimal-residual predictor, so it never needs more than one extra
+        # iteration per solve and usually needs fewer
+        assert np.all(it[k] <= ito + steps), (it[k], ito)
     p.close()
 
 
