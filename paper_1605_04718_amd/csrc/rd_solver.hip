@@ -354,26 +354,64 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
 
 // x' = x + d: hi (+ lo) absorb the increment.  kDGlobal: d is read from the
 // global array H (own-cell layout); otherwise d is in registers and is also
-// recorded in H (when non-null) for the next step's predictor.
+// recorded in H (when non-null) for the next step's predictor.  The global
+// loads are all issued before the first use: on this architecture stores
+// count in the same counter as loads, so a load placed after the previous
+// cell's store would wait for that store as well, one round trip per cell.
 template <int N, int R, int U, bool kDGlobal, typename Real, class Arr>
 __device__ __forceinline__ void fold(Arr &hi, Arr &d, Real *lo, Real *H, const Geo<N, R> &g)
 {
+    constexpr bool comp = Compensated<Real>::on;
     const int o = g.off();
+    if constexpr (R * sizeof(Real) > 32 * sizeof(float)) {
+        // long strips (streamed variant): one pass, the loads overlap with
+        // the other workgroups' work instead
 #pragma unroll U
+        for (int k = 0; k < R; ++k) {
+            const Real dk = kDGlobal ? H[o + k * N] : d[k];
+            if constexpr (comp) {
+                float s, e;
+                two_sum(hi[k], dk, s, e);
+                const float lk = lo[o + k * N] + e;
+                const float nh = s + lk;
+                hi[k] = nh;
+                lo[o + k * N] = lk - (nh - s);
+            } else {
+                hi[k] = hi[k] + dk;
+            }
+            if (!kDGlobal && H)
+                H[o + k * N] = dk;
+        }
+        return;
+    }
+    Real l[R], dd[R];
+#pragma unroll
     for (int k = 0; k < R; ++k) {
-        const Real dk = kDGlobal ? H[o + k * N] : d[k];
-        if constexpr (Compensated<Real>::on) {
+        if constexpr (comp)
+            l[k] = lo[o + k * N];
+        dd[k] = kDGlobal ? H[o + k * N] : d[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if constexpr (comp)
+            RD_PIN(l[k]);
+        RD_PIN(dd[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        if constexpr (comp) {
             float s, e;
-            two_sum(hi[k], dk, s, e);
-            const float l = lo[o + k * N] + e;
-            const float nh = s + l;
+            two_sum(hi[k], dd[k], s, e);
+            const float lk = l[k] + e;
+            const float nh = s + lk;
             hi[k] = nh;
-            lo[o + k * N] = l - (nh - s);
+            lo[o + k * N] = lk - (nh - s);
         } else {
-            hi[k] = hi[k] + dk;
+            hi[k] = hi[k] + dd[k];
         }
         if (!kDGlobal && H)
-            H[o + k * N] = dk;
+            H[o + k * N] = dd[k];
     }
 }
 
@@ -430,16 +468,23 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
     const double decay = gd.decay;
     double rho_m2 = 1.0;
     int st = 0;
+    // The predictor pays off only while the field moves: a species whose
+    // last solve needed no CG iteration skips it (its residual was already
+    // below the tolerance without it).
+    int last_u = 0, last_v = 0;
     for (int s = 0; s < n_steps; ++s, rho_m2 = uniform(rho_m2 * decay)) {
         const Real cu = uniform((Real)(rho_m2 * n2));
         const Real cv = uniform((Real)(th[3] * rho_m2 * n2));
+        const bool pred_u = s > 0 && last_u > 0;
+        const bool pred_v = s > 0 && last_v > 0;
+        const int itu0 = itu, itv0 = itv;
         if constexpr (kLds) {
             LdsArr<Real, N> sv{stash + g.idx(0)};
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 sv[k] = xv[k];
             st = cg_solve<N, R, U, NW, kLds, 0>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
-                                                maxit, P, lo_u, h_u, s > 0, red, g, itu);
+                                                maxit, P, lo_u, h_u, pred_u, red, g, itu);
 #pragma unroll U
             for (int k = 0; k < R; ++k) {
                 xv[k] = sv[k];
@@ -450,23 +495,25 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
                 break;
             store_increment<N, R, U>(d, h_u, g);
             st = cg_solve<N, R, U, NW, kLds, 1>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
-                                                maxit, P, lo_v, h_v, s > 0, red, g, itv);
+                                                maxit, P, lo_v, h_v, pred_v, red, g, itv);
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 xu[k] = sv[k];
         } else {
             st = cg_solve<N, R, U, NW, kLds, 0>(xu, xv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
-                                                maxit, P, lo_u, h_u, s > 0, red, g, itu);
+                                                maxit, P, lo_u, h_u, pred_u, red, g, itu);
             if (st)
                 break;
             store_increment<N, R, U>(d, h_u, g);
             st = cg_solve<N, R, U, NW, kLds, 1>(xv, xu, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
-                                                maxit, P, lo_v, h_v, s > 0, red, g, itv);
+                                                maxit, P, lo_v, h_v, pred_v, red, g, itv);
         }
         if (st)
             break;
         fold<N, R, U, false>(xv, d, lo_v, h_v, g);
         fold<N, R, U, true>(xu, d, lo_u, h_u, g);
+        last_u = uniform(itu - itu0);
+        last_v = uniform(itv - itv0);
     }
     return st;
 }
