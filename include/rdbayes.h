@@ -63,7 +63,8 @@ enum {
     RD_ST_NOT_CONVERGED = 1, /* CG reached cg_maxit */
     RD_ST_BREAKDOWN = 2,     /* p.Ap <= 0: the implicit operator lost definiteness */
     RD_ST_NONFINITE = 4,     /* NaN/Inf in a field or reduction */
-    RD_ST_OUT_OF_PRIOR = 8   /* proposal outside the prior box: not solved */
+    RD_ST_OUT_OF_PRIOR = 8,  /* proposal outside the prior box: not solved */
+    RD_ST_BAD_GRID = 16      /* grid_id outside [0, n_grids): not solved */
 };
 
 enum { RD_PRECISION_FP32 = 0, RD_PRECISION_FP64 = 1 };
@@ -114,17 +115,20 @@ int32_t destroy_problem(rd_problem *p);
 /* G(theta) for n parameter vectors (Sec. 2 observation operator): integrate
  * each from the initial fields of its grid class to T.
  *   theta    dev float64 [n][4] natural parameters (a, b, gamma, d)
- *   grid_id  dev int32 [n] grid class of each item, or NULL (class 0)
- *   u_out    dev [n][N*N] final u (float32 for FP32 problems, float64 for
- *            FP64 problems), or NULL; only allowed when every item has the
- *            same grid size N (pass N = the size of grid 0)
+ *   grid_id  dev int32 [n] grid class of each item, or NULL (class 0).
+ *            With several classes the batch runs as one persistent launch
+ *            over all classes, largest grids first; an id outside
+ *            [0, n_grids) marks the item RD_ST_BAD_GRID (not solved).
+ *   u_out    dev [n][M*M] final u (float32 for FP32 problems, float64 for
+ *            FP64 problems), M = the largest grid size of the problem; item
+ *            c of size N occupies the first N*N values of row c (row-major,
+ *            x fastest).  NULL: not written.
  *   v_out    same layout for v, or NULL
  *   status   dev int32 [n] RD_ST_* bits (0 = success), required
  *   cg_iters dev int32 [n][2] total CG iterations of the u and v systems,
  *            or NULL
  * n = 0 is a no-op (array arguments may then be NULL).
- * Errors: RD_EINVAL (n < 0 or n > max_batch, NULL status, mixed sizes with
- * field outputs). */
+ * Errors: RD_EINVAL (n < 0 or n > max_batch, NULL status). */
 int32_t forward_solve_batch(rd_problem *p, int32_t n, const double *theta,
                             const int32_t *grid_id, void *u_out, void *v_out,
                             int32_t *status, int32_t *cg_iters, void *stream);
@@ -247,8 +251,15 @@ int32_t surrogate_params(rd_problem *p, int32_t layer, float *w, float *b, int32
 
 /* Re-runs the tile-shape autotuner for every grid class of p (a few timed
  * trial solves) and keeps the fastest; returns the chosen cells-per-thread
- * of each class in cpt_out (host int32 [n_grids], may be NULL). */
+ * of each class in cpt_out (host int32 [n_grids], may be NULL).  With
+ * several grid classes it also times the mixed-class launch at 512 and 1024
+ * threads per workgroup and keeps the faster (see rd_mixed_threads).  The
+ * choice is cached per device, grid size and precision for later problems. */
 int32_t rd_autotune(rd_problem *p, int32_t *cpt_out);
+
+/* Workgroup size of the launch that serves batches mixing grid classes
+ * (host int32 out).  Errors: RD_EINVAL (NULL argument). */
+int32_t rd_mixed_threads(const rd_problem *p, int32_t *threads);
 
 /* Accumulated device time (ms, measured with HIP events on the launch
  * stream) and launch count of the fused solve kernel since the last reset;

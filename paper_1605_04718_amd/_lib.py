@@ -60,6 +60,7 @@ SYMBOLS = {
     "surrogate_params": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_vp]),
     "rd_autotune": (c_i32, [c_vp, c_vp]),
     "rd_solver_timing": (c_i32, [c_vp, c_i32, c_dp, ctypes.POINTER(c_i64), c_i32]),
+    "rd_mixed_threads": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),
     "rd_status_string": (ctypes.c_char_p, [c_i32]),
     "rd_last_error": (ctypes.c_char_p, []),
 }

@@ -114,12 +114,17 @@ class Problem:
 
     # -- forward map and likelihood -------------------------------------
     def forward_solve(self, theta, grid_id=None, fields=True, stream=None):
-        """theta: HIP float64 [n, 4] (a, b, gamma, d).  Returns (u, v, status, iters)."""
+        """theta: HIP float64 [n, 4] (a, b, gamma, d).  Returns (u, v, status, iters).
+
+        With one grid class u, v are [n, N, N]; with several they are
+        [n, M*M] (M the largest size) and item c of size N is
+        u[c, :N*N].view(N, N)."""
         n = theta.shape[0]
-        N = self.grids[0].n
+        M = max(g.n for g in self.grids)
+        shape = (n, M, M) if len(self.grids) == 1 else (n, M * M)
         dev = theta.device
-        u = torch.empty((n, N, N), dtype=self.field_dtype, device=dev) if fields else None
-        v = torch.empty((n, N, N), dtype=self.field_dtype, device=dev) if fields else None
+        u = torch.empty(shape, dtype=self.field_dtype, device=dev) if fields else None
+        v = torch.empty(shape, dtype=self.field_dtype, device=dev) if fields else None
         st = torch.empty(n, dtype=torch.int32, device=dev)
         it = torch.empty((n, 2), dtype=torch.int32, device=dev)
         check(lib().forward_solve_batch(self.h, n, _ptr(theta), _ptr(grid_id), _ptr(u), _ptr(v),
@@ -227,6 +232,12 @@ class Problem:
         out = (ctypes.c_int32 * len(self.grids))()
         check(lib().rd_autotune(self.h, ctypes.cast(out, ctypes.c_void_p)), "rd_autotune")
         return list(out)
+
+    def mixed_threads(self):
+        """Workgroup size of the launch that serves batches mixing grid classes."""
+        t = ctypes.c_int32()
+        check(lib().rd_mixed_threads(self.h, ctypes.byref(t)), "rd_mixed_threads")
+        return t.value
 
     def solver_timing(self, enable=True, reset=False):
         ms = ctypes.c_double()

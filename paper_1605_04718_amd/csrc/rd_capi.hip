@@ -71,7 +71,14 @@ struct rd_problem {
     std::vector<void *> allocs;
     TileChoice tile[RD_MAX_GRIDS]{};
     int wgs_per_cu[RD_MAX_GRIDS]{};  // resident workgroups per CU of tile[g]
+    // batches that mix grid classes: one persistent launch of this many
+    // threads per workgroup, queue ordered by class cost
+    int mixed_threads = 1024;
+    int mixed_wpc = 1;
+    RankTable rank{};
+    int *order_ws = nullptr;
     int maxit = 0;
+    int max_n = 0;  // largest class: field outputs have max_n^2 values per item
     // workspace [max_batch]
     unsigned *queue = nullptr;
     double *theta_prop = nullptr;
@@ -183,12 +190,12 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
 {
     if (n == 0)
         return RD_OK;
-    if (p->desc.n_grids != 1 && grid_id)
-        return fail(RD_EUNSUPPORTED, "mixed grid classes are served by the mixed solve");
+    const bool mixed = p->desc.n_grids > 1 && grid_id;
     const int g = 0;
     const int nn = p->grids_host[g].n;
     SolveArgs a{};
     a.grids = p->grids_dev;
+    a.n_grids = p->desc.n_grids;
     a.n_items = n;
     a.order = nullptr;
     a.grid_id = grid_id;
@@ -203,6 +210,7 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     a.iters = iters;
     a.u_out = u_out;
     a.v_out = v_out;
+    a.out_stride = (size_t)p->max_n * p->max_n;
     a.queue = p->queue;
     a.gws = p->gws;
     a.gws_stride = p->gws_stride;
@@ -210,13 +218,20 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     const TileChoice t = p->tile[g];
     // wgs_per_cu was queried when the tile was chosen: no runtime query may
     // run here, since this is also called while a stream is being captured.
-    int wgs = p->n_cu * p->wgs_per_cu[g];
+    int wgs = p->n_cu * (mixed ? p->mixed_wpc : p->wgs_per_cu[g]);
     if (wgs > n)
         wgs = n;
     HIP_TRY(launch_fill_u32(p->queue, 0u, 1, s));
+    if (mixed) {
+        HIP_TRY(launch_class_order(grid_id, n, p->desc.n_grids, p->rank, p->order_ws, s));
+        a.order = p->order_ws;
+    }
     hipEvent_t e0;
     HIP_TRY(record_solve_start(p, s, &e0));
-    HIP_TRY(launch_solve(nn, p->desc.precision, t, a, wgs, s));
+    if (mixed)
+        HIP_TRY(launch_solve_mixed(p->desc.precision, p->mixed_threads, a, wgs, s));
+    else
+        HIP_TRY(launch_solve(nn, p->desc.precision, t, a, wgs, s));
     HIP_TRY(record_solve_end(p, s, e0));
     return RD_OK;
 }
@@ -336,6 +351,9 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         const rd_grid_desc &gd = desc->grids[g];
         if (!tile_supported(gd.n, desc->precision, default_cpt(gd.n, desc->precision)))
             return fail(RD_EUNSUPPORTED, "grid %d: n = %d has no kernel at this precision", g, gd.n);
+        if (desc->n_grids > 1 &&
+            !(mixed_supported(gd.n, desc->precision, 512) && mixed_supported(gd.n, desc->precision, 1024)))
+            return fail(RD_EUNSUPPORTED, "grid %d: n = %d cannot join a mixed batch", g, gd.n);
         if (!gd.u0 || !gd.v0)
             return fail(RD_EINVAL, "grid %d: u0 and v0 are required", g);
         if (gd.growth != 0 && gd.growth != 1)
@@ -392,6 +410,7 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         p->wgs_per_cu[g] = solve_wgs_per_cu(gd.n, desc->precision, cpt);
     }
     p->maxit = desc->cg_maxit > 0 ? desc->cg_maxit : 10 * max_n * max_n;
+    p->max_n = max_n;
     const int B = desc->max_batch;
     p->grids_dev = (GridDev *)dmalloc(p, sizeof(GridDev) * desc->n_grids, &err);
     p->queue = (unsigned *)dmalloc(p, 64, &err);
@@ -416,8 +435,8 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         return fail(RD_EHIP, "upload of grid table failed");
     }
     // Solve workspace: one slot per resident workgroup, sized for every tile
-    // the autotuner may pick (the predictor history, 2 n^2 values, and for
-    // streamed tiles the 7 strip arrays as well).
+    // the autotuner may pick (low parts and predictor history, 4 n^2 values,
+    // and for streamed tiles the 6 strip arrays as well).
     size_t slot = 0;
     int slots = 0;
     for (int g = 0; g < desc->n_grids; ++g) {
@@ -428,6 +447,31 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
                 slots = std::max(slots, p->n_cu * solve_wgs_per_cu(n, desc->precision, cpt));
             }
         }
+        if (desc->n_grids > 1) {
+            for (int threads : {512, 1024}) {
+                slot = std::max(slot, mixed_slot_bytes(n, desc->precision, threads));
+                slots = std::max(slots, p->n_cu * mixed_wgs_per_cu(desc->precision, threads));
+            }
+        }
+    }
+    if (desc->n_grids > 1) {
+        // queue order: larger grids first (cost per solve ~ cells)
+        std::vector<int> cls(desc->n_grids);
+        for (int g = 0; g < desc->n_grids; ++g)
+            cls[g] = g;
+        std::stable_sort(cls.begin(), cls.end(), [&](int x, int y) {
+            return p->grids_host[x].n > p->grids_host[y].n;
+        });
+        for (int k = 0; k < desc->n_grids; ++k)
+            p->rank.r[cls[k]] = k;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find(tune_key(p->device, -1, desc->precision));
+            if (it != g_tuned.end())
+                p->mixed_threads = it->second;
+        }
+        p->mixed_wpc = mixed_wgs_per_cu(desc->precision, p->mixed_threads);
+        p->order_ws = (int *)dmalloc(p, sizeof(int) * desc->max_batch, &err);
     }
     slot = (slot + 255) / 256 * 256;
     p->gws = dmalloc(p, slot * (size_t)slots, &err);
@@ -507,12 +551,13 @@ extern "C" int32_t field_misfit_batch(rd_problem *p, int32_t n, const void *u,
         return r;
     if (n > 0 && (!u || !phi))
         return fail(RD_EINVAL, "u and phi are required");
-    if (p->desc.n_grids != 1 && grid_id)
-        return fail(RD_EUNSUPPORTED, "field_misfit_batch takes one grid size");
+    if (p->desc.n_grids != 1)
+        return fail(RD_EUNSUPPORTED, "field_misfit_batch takes problems with one grid class");
     if (!p->grids_host[0].y)
         return fail(RD_EINVAL, "grid 0 has no data y");
+    (void)grid_id;  // one class: every field is compared with grid 0's data
     const int npts = p->grids_host[0].n * p->grids_host[0].n;
-    HIP_TRY(launch_field_misfit(p->desc.precision, p->grids_dev, grid_id, n, npts, u, phi,
+    HIP_TRY(launch_field_misfit(p->desc.precision, p->grids_dev, nullptr, n, npts, u, phi,
                                 (hipStream_t)stream));
     return RD_OK;
 }
@@ -716,7 +761,86 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
         if (cpt_out)
             cpt_out[g] = best;
     }
+    if (p->desc.n_grids > 1) {
+        // Mixed launch: workgroup size, on a batch that cycles through the
+        // classes (one item per workgroup slot).
+        int best = p->mixed_threads;
+        float best_ms = 1e30f;
+        for (int threads : {512, 1024}) {
+            const int wpc = mixed_wgs_per_cu(p->desc.precision, threads);
+            const int items = std::min(p->desc.max_batch, p->n_cu * wpc);
+            std::vector<double> th(4 * items);
+            std::vector<int> gid(items);
+            for (int k = 0; k < items; ++k) {
+                th[4 * k + 0] = 0.5 * (p->desc.lo[0] + p->desc.hi[0]);
+                th[4 * k + 1] = 0.5 * (p->desc.lo[1] + p->desc.hi[1]);
+                th[4 * k + 2] = exp(0.5 * (p->desc.lo[2] + p->desc.hi[2]));
+                th[4 * k + 3] = exp(0.5 * (p->desc.lo[3] + p->desc.hi[3]));
+                gid[k] = k % p->desc.n_grids;
+            }
+            double *d_th = nullptr;
+            int *d_st = nullptr, *d_gid = nullptr;
+            HIP_TRY(hipMalloc(&d_th, sizeof(double) * th.size()));
+            HIP_TRY(hipMalloc(&d_st, sizeof(int) * items));
+            HIP_TRY(hipMalloc(&d_gid, sizeof(int) * items));
+            HIP_TRY(hipMemcpy(d_th, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(d_gid, gid.data(), sizeof(int) * items, hipMemcpyHostToDevice));
+            const int saved_threads = p->mixed_threads, saved_wpc = p->mixed_wpc;
+            const int saved_steps = p->desc.n_steps;
+            p->mixed_threads = threads;
+            p->mixed_wpc = wpc;
+            p->desc.n_steps = trial_steps;
+            const bool saved_timing = p->timing;
+            p->timing = false;
+            hipEvent_t e0, e1;
+            hipEventCreate(&e0);
+            hipEventCreate(&e1);
+            int32_t r = enqueue_solve(p, items, d_th, d_gid, nullptr, nullptr, d_st, nullptr,
+                                      nullptr, nullptr, nullptr);
+            hipEventRecord(e0, nullptr);
+            if (r == RD_OK)
+                r = enqueue_solve(p, items, d_th, d_gid, nullptr, nullptr, d_st, nullptr, nullptr,
+                                  nullptr, nullptr);
+            hipEventRecord(e1, nullptr);
+            hipEventSynchronize(e1);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            p->timing = saved_timing;
+            p->desc.n_steps = saved_steps;
+            p->mixed_threads = saved_threads;
+            p->mixed_wpc = saved_wpc;
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            hipFree(d_th);
+            hipFree(d_st);
+            hipFree(d_gid);
+            if (r != RD_OK)
+                return r;
+            const float per_item = ms / (float)items;
+            if (getenv("RDBAYES_AUTOTUNE_VERBOSE"))
+                fprintf(stderr, "[rd_autotune] mixed prec=%d threads=%d wgs/cu=%d: %.4f ms/item\n",
+                        p->desc.precision, threads, wpc, per_item);
+            if (per_item < best_ms) {
+                best_ms = per_item;
+                best = threads;
+            }
+        }
+        p->mixed_threads = best;
+        p->mixed_wpc = mixed_wgs_per_cu(p->desc.precision, best);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[tune_key(p->device, -1, p->desc.precision)] = best;
+        }
+    }
     drop_graphs(p);
+    return RD_OK;
+}
+
+extern "C" int32_t rd_mixed_threads(const rd_problem *p, int32_t *threads)
+{
+    if (!p || !threads)
+        return fail(RD_EINVAL, "problem and threads are required");
+    *threads = p->mixed_threads;
     return RD_OK;
 }
 
@@ -759,6 +883,7 @@ extern "C" const char *rd_status_string(int32_t s)
     case RD_ST_BREAKDOWN: return "CG breakdown (operator not positive definite)";
     case RD_ST_NONFINITE: return "non-finite value";
     case RD_ST_OUT_OF_PRIOR: return "outside the prior box";
+    case RD_ST_BAD_GRID: return "grid id outside [0, n_grids)";
     default: return "combination of status flags";
     }
 }

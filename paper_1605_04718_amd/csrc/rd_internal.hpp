@@ -5,7 +5,13 @@
 
 namespace rd {
 
-enum : int { kStNotConverged = 1, kStBreakdown = 2, kStNonfinite = 4, kStOutOfPrior = 8 };
+enum : int {
+    kStNotConverged = 1,
+    kStBreakdown = 2,
+    kStNonfinite = 4,
+    kStOutOfPrior = 8,
+    kStBadGrid = 16
+};
 
 // One grid class as the kernels see it (device memory).
 struct GridDev {
@@ -25,6 +31,7 @@ struct GridDev {
 // Arguments of one fused solve launch.
 struct SolveArgs {
     const GridDev *grids;    // device array [n_grids]
+    int n_grids;
     int n_items;             // queue length
     const int *order;        // item -> index into the batch (null: identity)
     const int *grid_id;      // batch index -> grid class (null: 0)
@@ -37,13 +44,21 @@ struct SolveArgs {
     double *phi;             // [n] misfit out (null: skip misfit)
     int *status;             // [n] status out (required)
     int *iters;              // [n][2] CG iteration totals (null: skip)
-    void *u_out;             // [n][N*N] final u (null: skip)
-    void *v_out;             // [n][N*N] final v (null: skip)
+    void *u_out;             // [n][out_stride] final u, first N*N values of a row
+                             // (null: skip)
+    void *v_out;             // same layout, final v
+    size_t out_stride;       // values per item in u_out / v_out
     unsigned *queue;         // work-queue head (zeroed before the launch)
     void *gws;               // per-workgroup workspace slots (predictor history,
                              // streamed strip arrays)
     size_t gws_stride;       // bytes per slot
     int gws_slots;           // number of slots
+};
+
+// Class ranks of a mixed batch (queue order: rank 0 first).
+constexpr int kMaxClasses = 8;
+struct RankTable {
+    int r[kMaxClasses];
 };
 
 // Solver tile choices: cells per thread (rows of the strip a thread owns).
@@ -55,7 +70,13 @@ struct TileChoice {
 // Host launchers (rd_solver.hip).
 hipError_t launch_solve(int n, int precision, TileChoice tile, const SolveArgs &a, int grid_wgs,
                         hipStream_t s);
-hipError_t launch_solve_mixed(int precision, const SolveArgs &a, int grid_wgs, hipStream_t s);
+hipError_t launch_solve_mixed(int precision, int threads, const SolveArgs &a, int grid_wgs,
+                              hipStream_t s);
+hipError_t launch_class_order(const int *grid_id, int n, int n_grids, const RankTable &rank,
+                              int *order, hipStream_t s);
+bool mixed_supported(int n, int precision, int threads);
+size_t mixed_slot_bytes(int n, int precision, int threads);
+int mixed_wgs_per_cu(int precision, int threads);
 bool tile_supported(int n, int precision, int cpt);
 bool tile_streamed(int n, int precision, int cpt);
 int solve_wgs_per_cu(int n, int precision, int cpt);

@@ -546,7 +546,7 @@ __device__ void finish_item(const SolveArgs &a, const GridDev &gd, int c, Arr &x
     using L = SlotLayout<Real>;
     constexpr int NW = (N * N / R) / kWave;
     constexpr int U = (R <= 32) ? R : 4;
-    const size_t off = (size_t)c * N * N;
+    const size_t off = (size_t)c * a.out_stride;
     if (a.u_out) {
 #pragma unroll U
         for (int k = 0; k < R; ++k)
@@ -595,6 +595,63 @@ __device__ __forceinline__ int next_item(unsigned *queue, int *s_item)
     return uniform(*s_item);
 }
 
+// Grid class of batch index c, or -1 (and the item is marked failed) when
+// grid_id is outside [0, n_grids).
+__device__ __forceinline__ int item_grid(const SolveArgs &a, int c)
+{
+    const int gid = uniform(a.grid_id ? a.grid_id[c] : 0);
+    if ((unsigned)gid < (unsigned)a.n_grids)
+        return gid;
+    if (threadIdx.x == 0) {
+        a.status[c] = kStBadGrid;
+        if (a.phi)
+            a.phi[c] = __builtin_inf();
+    }
+    return -1;
+}
+
+// One item, resident variant: P and stash are LDS arrays of at least N*N.
+template <int N, int R, typename Real>
+__device__ __forceinline__ void solve_item_resident(const SolveArgs &a, int c, const GridDev &gd,
+                                                    Real *P, Real *stash, double *red, Real *slot)
+{
+    constexpr int NW = (N * N / R) / kWave;
+    const Geo<N, R> g;
+    const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
+                          a.theta[4 * c + 3]};
+    RegArr<Real, R> xu, xv, r, q, d;
+    load_initial<N, R, R>(gd, xu, xv, slot, g);
+    int itu = 0, itv = 0;
+    const int st = integrate<N, R, R, NW, true>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps, a.rtol2,
+                                                a.maxit, P, stash, slot, red, g, itu, itv);
+    finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
+}
+
+// One item, streamed variant: the strip arrays and p follow the SlotLayout
+// arrays in the workgroup's global slot.
+template <int N, int R, typename Real>
+__device__ __forceinline__ void solve_item_streamed(const SolveArgs &a, int c, const GridDev &gd,
+                                                    double *red, Real *slot)
+{
+    constexpr int NW = (N * N / R) / kWave;
+    constexpr int U = 4;
+    constexpr size_t NN = (size_t)N * N;
+    const Geo<N, R> g;
+    Real *arr = slot + SlotLayout<Real>::arrays * NN;
+    Real *P = arr + 5 * NN;
+    const int base = g.j0 * N + g.i;
+    GlobArr<Real, N> xu{arr + base}, xv{arr + NN + base}, r{arr + 2 * NN + base},
+        q{arr + 3 * NN + base}, d{arr + 4 * NN + base};
+    const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
+                          a.theta[4 * c + 3]};
+    load_initial<N, R, U>(gd, xu, xv, slot, g);
+    int itu = 0, itv = 0;
+    const int st = integrate<N, R, U, NW, false>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps, a.rtol2,
+                                                 a.maxit, P, (Real *)nullptr, slot, red, g, itu,
+                                                 itv);
+    finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
+}
+
 template <int N, int R, typename Real>
 __global__ __launch_bounds__(N *N / R) void k_solve_resident(SolveArgs a)
 {
@@ -603,58 +660,127 @@ __global__ __launch_bounds__(N *N / R) void k_solve_resident(SolveArgs a)
     __shared__ Real stash[N * N];
     __shared__ double red[Slots<NW>::total];
     __shared__ int s_item;
-    const Geo<N, R> g;
     Real *slot = (Real *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
     for (int item = next_item(a.queue, &s_item); item < a.n_items;
          item = next_item(a.queue, &s_item)) {
         const int c = uniform(a.order ? a.order[item] : item);
         if (!a.need || uniform(a.need[c])) {
-            const GridDev &gd = a.grids[uniform(a.grid_id ? a.grid_id[c] : 0)];
-            const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
-                                  a.theta[4 * c + 3]};
-            RegArr<Real, R> xu, xv, r, q, d;
-            load_initial<N, R, R>(gd, xu, xv, slot, g);
-            int itu = 0, itv = 0;
-            const int st = integrate<N, R, R, NW, true>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps,
-                                                  a.rtol2, a.maxit, P, stash, slot, red, g, itu,
-                                                  itv);
-            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
+            const int gid = item_grid(a, c);
+            if (gid >= 0)
+                solve_item_resident<N, R, Real>(a, c, a.grids[gid], P, stash, red, slot);
         }
     }
 }
 
-// Streamed variant: the strip arrays and p follow the SlotLayout arrays in
-// the workgroup's global slot.
 template <int N, int R, typename Real>
 __global__ __launch_bounds__(N *N / R) void k_solve_streamed(SolveArgs a)
 {
     constexpr int NW = (N * N / R) / kWave;
-    constexpr int U = 4;
-    constexpr size_t NN = (size_t)N * N;
     __shared__ double red[Slots<NW>::total];
     __shared__ int s_item;
-    const Geo<N, R> g;
     Real *slot = (Real *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
-    Real *arr = slot + SlotLayout<Real>::arrays * NN;
-    Real *P = arr + 5 * NN;
-    const int base = g.j0 * N + g.i;
-    GlobArr<Real, N> xu{arr + base}, xv{arr + NN + base}, r{arr + 2 * NN + base},
-        q{arr + 3 * NN + base}, d{arr + 4 * NN + base};
     for (int item = next_item(a.queue, &s_item); item < a.n_items;
          item = next_item(a.queue, &s_item)) {
         const int c = uniform(a.order ? a.order[item] : item);
         if (!a.need || uniform(a.need[c])) {
-            const GridDev &gd = a.grids[uniform(a.grid_id ? a.grid_id[c] : 0)];
-            const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
-                                  a.theta[4 * c + 3]};
-            load_initial<N, R, U>(gd, xu, xv, slot, g);
-            int itu = 0, itv = 0;
-            const int st = integrate<N, R, U, NW, false>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps,
-                                                  a.rtol2, a.maxit, P, (Real *)nullptr, slot, red,
-                                                  g, itu, itv);
-            finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
+            const int gid = item_grid(a, c);
+            if (gid >= 0)
+                solve_item_streamed<N, R, Real>(a, c, a.grids[gid], red, slot);
         }
     }
+}
+
+// Uneven batches: one persistent launch of T-thread workgroups serves items
+// of every grid class.  Each class runs the strip layout that T threads give
+// it (R = n^2 / T cells per thread): resident where its arrays fit the VGPR
+// and LDS budget, streamed otherwise.  The queue is ordered by decreasing
+// cost (a.order), so that the large solves start first and the small ones
+// fill the tail.
+template <typename Real>
+struct MixedTraits {
+    static constexpr int kMaxResident = sizeof(Real) == 4 ? 128 : 64;
+};
+
+template <int N, int T, typename Real>
+__device__ __forceinline__ void solve_item_class(const SolveArgs &a, int c, const GridDev &gd,
+                                                 Real *P, Real *stash, double *red, Real *slot)
+{
+    if constexpr (N * N >= T) {
+        constexpr int R = N * N / T;
+        if constexpr (N <= MixedTraits<Real>::kMaxResident && R <= 32 / (sizeof(Real) / 4))
+            solve_item_resident<N, R, Real>(a, c, gd, P, stash, red, slot);
+        else
+            solve_item_streamed<N, R, Real>(a, c, gd, red, slot);
+    }
+}
+
+template <int T, typename Real>
+__global__ __launch_bounds__(T) void k_solve_mixed(SolveArgs a)
+{
+    constexpr int NW = T / kWave;
+    constexpr int NM = MixedTraits<Real>::kMaxResident;
+    __shared__ Real P[NM * NM];
+    __shared__ Real stash[NM * NM];
+    __shared__ double red[Slots<NW>::total];
+    __shared__ int s_item;
+    Real *slot = (Real *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
+    for (int item = next_item(a.queue, &s_item); item < a.n_items;
+         item = next_item(a.queue, &s_item)) {
+        const int c = uniform(a.order ? a.order[item] : item);
+        const int gid = (!a.need || uniform(a.need[c])) ? item_grid(a, c) : -1;
+        if (gid >= 0) {
+            const GridDev &gd = a.grids[gid];
+            const int n = uniform(gd.n);
+            if (n == 32)
+                solve_item_class<32, T, Real>(a, c, gd, P, stash, red, slot);
+            else if (n == 64)
+                solve_item_class<64, T, Real>(a, c, gd, P, stash, red, slot);
+            else if (n == 128)
+                solve_item_class<128, T, Real>(a, c, gd, P, stash, red, slot);
+            else if (n == 256)
+                solve_item_class<256, T, Real>(a, c, gd, P, stash, red, slot);
+        }
+    }
+}
+
+// Queue order of a mixed batch: the stable counting sort of the items by
+// grid class in the order `rank` (rank[g] = position of class g, most costly
+// first).  One workgroup; thread t sorts a contiguous chunk.
+__device__ __forceinline__ int class_rank(const RankTable &rank, int gid, int n_grids)
+{
+    return (unsigned)gid < (unsigned)n_grids ? rank.r[gid] : kMaxClasses - 1;
+}
+
+__global__ __launch_bounds__(1024) void k_class_order(const int *grid_id, int n, int n_grids,
+                                                      RankTable rank, int *order)
+{
+    __shared__ int counts[1024][kMaxClasses];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int lo = t * chunk, hi = min(n, lo + chunk);
+    int local[kMaxClasses];
+    for (int g = 0; g < kMaxClasses; ++g)
+        local[g] = 0;
+    for (int i = lo; i < hi; ++i)
+        local[class_rank(rank, grid_id[i], n_grids)]++;
+    for (int g = 0; g < kMaxClasses; ++g)
+        counts[t][g] = local[g];
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int g = 0; g < kMaxClasses; ++g) {
+            for (int u = 0; u < 1024; ++u) {
+                const int v = counts[u][g];
+                counts[u][g] = run;
+                run += v;
+            }
+        }
+    }
+    __syncthreads();
+    for (int g = 0; g < kMaxClasses; ++g)
+        local[g] = counts[t][g];
+    for (int i = lo; i < hi; ++i)
+        order[local[class_rank(rank, grid_id[i], n_grids)]++] = i;
 }
 
 // Per-class time-stepping coefficients of the growing domain rho = exp(r t):
@@ -789,6 +915,60 @@ int solve_wgs_per_cu(int n, int precision, int cpt)
 #undef RD_OCC_R
 #undef RD_OCC_S
     return 1;
+}
+
+// Mixed launch: T threads per workgroup for every class.
+static bool mixed_resident(int n, int precision, int threads)
+{
+    const int r = n * n / threads;
+    return n <= (precision ? 64 : 128) && r <= (precision ? 16 : 32);
+}
+
+bool mixed_supported(int n, int precision, int threads)
+{
+    return (threads == 512 || threads == 1024) && (n == 32 || n == 64 || n == 128 || n == 256) &&
+           n * n >= threads;
+}
+
+size_t mixed_slot_bytes(int n, int precision, int threads)
+{
+    const size_t arrays = mixed_resident(n, precision, threads) ? 4 : 10;
+    return arrays * n * n * (precision ? sizeof(double) : sizeof(float));
+}
+
+int mixed_wgs_per_cu(int precision, int threads)
+{
+    if (precision == 0)
+        return threads == 512 ? occupancy(k_solve_mixed<512, float>, 512)
+                              : occupancy(k_solve_mixed<1024, float>, 1024);
+    return threads == 512 ? occupancy(k_solve_mixed<512, double>, 512)
+                          : occupancy(k_solve_mixed<1024, double>, 1024);
+}
+
+hipError_t launch_class_order(const int *grid_id, int n, int n_grids, const RankTable &rank,
+                              int *order, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_class_order, dim3(1), dim3(1024), 0, s, grid_id, n, n_grids, rank, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_mixed(int precision, int threads, const SolveArgs &a, int wgs,
+                              hipStream_t s)
+{
+    if (!a.gws || wgs > a.gws_slots || !a.order)
+        return hipErrorInvalidValue;
+    if (precision == 0) {
+        if (threads == 512)
+            hipLaunchKernelGGL((k_solve_mixed<512, float>), dim3(wgs), dim3(512), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_solve_mixed<1024, float>), dim3(wgs), dim3(1024), 0, s, a);
+    } else {
+        if (threads == 512)
+            hipLaunchKernelGGL((k_solve_mixed<512, double>), dim3(wgs), dim3(512), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_solve_mixed<1024, double>), dim3(wgs), dim3(1024), 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 bool tile_streamed(int n, int precision, int cpt)
