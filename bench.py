@@ -1,18 +1,27 @@
-"""Benchmark: batched plain Metropolis sampler on the 128x128 Schnakenberg problem.
+"""Benchmark: batched Metropolis on the 128x128 Schnakenberg problem, plain
+and with a surrogate first stage (delayed acceptance).
 
-One step = one Metropolis step (Algorithm 1) of every chain: proposal,
-fused IMEX/CG forward solve + Gaussian misfit of every in-box proposal,
-accept/reject.  Workload (the batched-plain-sampler configuration): 4096
+One step = one Metropolis step (Algorithm 1) of every chain: proposal, fused
+IMEX/CG forward solve + Gaussian misfit of every in-box proposal,
+accept/reject.  Workload (the batched plain-sampler configuration): 4096
 chains, 128 x 128 cells, FP32 fields with FP64 reductions, four free
 parameters (a, b, ln gamma, ln d) with a uniform prior box a, b in [0, 1],
 gamma in [50, 500], d in [5, 50] (log-uniform), proposal s.d. 2 % of each
 box side, T = 2, synthetic data from theta = (0.1, 0.9, 200, 10) with 1 %
-Gaussian noise.  The time step is 2.5e-4 (8000 steps): at dt = 1e-3 the
-Picard-linearised IMEX step is unstable for the homogeneous mode at this
-theta (gamma dt above |f_u + g_v| / ((a+b)(2b-a)) = 0.118).
+Gaussian noise, chains started from prior draws.  The time step is 2.5e-4
+(8000 steps): at dt = 1e-3 the Picard-linearised IMEX step is unstable for
+the homogeneous mode at this theta (gamma dt above
+|f_u + g_v| / ((a+b)(2b-a)) = 0.118).
 
-Prints one JSON line (metric: PDE cell-steps per second, plus ESS/s, the
-roofline of the fused solve kernel and the FP64 CPU oracle baseline).
+The delayed-acceptance leg trains the surrogate (BF16 MFMA MLP 4-512x4-1024)
+on a bounded number of the library's own prior solves first, then runs the
+same number of steps from the same chain states: every proposal is screened
+by the surrogate and only stage-1 passes are solved.
+
+Prints one JSON line: value = PDE cell-steps per second of the plain
+sampler (solves actually performed), the roofline of the fused solve
+kernel, the FP64 CPU oracle baseline, and the delayed-acceptance figures
+beside the plain ones.
 """
 from __future__ import annotations
 
@@ -38,12 +47,21 @@ CG_RTOL = 1e-7
 CG_MAXIT = 400
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed); FLOP/s
 # Algorithmic FP operations of the fused solve (per cell, per species):
-#   one CG iteration: stencil q = sigma p + c sum(p - p_nb) (10), p.q (2),
-#   r -= alpha q (2), r.r (2), x += alpha p (2), p = r + beta p (2) -> 20
-#   one step's set-up: reaction diagonal (4), residual r0 (10), b and the two
-#   norms (6) -> 20
-FLOP_CG_ITER = 20.0
-FLOP_SETUP = 20.0
+#   one CG iteration: 5-point differences (7), reaction diagonal (2),
+#   q = sigma p + c t (2), p.q (2), r -= alpha q (1), r.r (2),
+#   d += alpha p (1), p = r + beta p (1) -> 18
+#   one step's set-up: residual of the high part (14: differences 7,
+#   diagonal 2, residual 2, right-hand side 1, its norm 2), of the low part
+#   (14) and the compensated fold of the increment (10) -> 38 (the optional
+#   predictor sweep is not counted)
+FLOP_CG_ITER = 18.0
+FLOP_SETUP = 38.0
+# HBM bytes of the fused solve kernel from two rocprofv3 PMC passes over the
+# timed step of `bench.py --steps 1 --warmup 0 --no-da --no-cpu-baseline`
+# (3831 solves): FETCH_SIZE 3 690 661 513 KiB x 2.00 + WRITE_SIZE
+# 7 467 109 936 KiB x 1.00 (factors from a 256 MiB copy), per solve-step.
+# Valid only for the kernel version and tile it was measured on.
+MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 496110.52445001306}
 
 
 def log(msg):
@@ -67,8 +85,52 @@ def cpu_baseline(u0, v0, y, sigma, n_steps_sample, threads):
     return dict(value=cell_steps / dt, unit="cell-steps/s", cores=threads, kind="oracle",
                 sample=f"{threads} prior draws (one per thread), first {n_steps_sample} of "
                        f"{int(round(T_FINAL / TAU))} IMEX steps at {N_CELLS}x{N_CELLS}, FP64, "
-                       f"rtol {CG_RTOL}; {dt:.1f} s wall; mean CG iters/step "
-                       f"u {it[:, 0].mean() / n_steps_sample:.1f} v {it[:, 1].mean() / n_steps_sample:.1f}")
+                       f"rtol {CG_RTOL}, start vector = previous level; {dt:.1f} s wall; mean "
+                       f"CG iters/step u {it[:, 0].mean() / n_steps_sample:.1f} "
+                       f"v {it[:, 1].mean() / n_steps_sample:.1f} (the early steps, where the "
+                       f"fields move fastest, cost more iterations than the run average)")
+
+
+def run_leg(p, ch, mode, warmup, steps, stream, name):
+    """Warm-up then timed Metropolis steps; returns the leg's counters."""
+    import torch
+    with torch.cuda.stream(stream):
+        for k in range(warmup):
+            t = time.time()
+            p.mcmc_step(ch, 1, mode=mode)
+            stream.synchronize()
+            log(f"{name} warmup step {k}: {time.time() - t:.2f} s")
+        solves0 = int(ch.n_solves.sum())
+        iters0 = ch.cg_iters.sum(0).cpu().numpy().astype(np.float64)
+        acc0 = int(ch.n_accept.sum())
+        acc10 = int(ch.n_accept1.sum())
+        p.solver_timing(enable=True, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for k in range(steps):
+            p.mcmc_step(ch, 1, mode=mode)
+            stream.synchronize()
+            log(f"{name} timed step {k}: {time.time() - t0:.2f} s elapsed")
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+    kern_ms, launches = p.solver_timing(enable=False)
+    return dict(wall=wall, kern_ms=kern_ms, launches=launches,
+                solves=int(ch.n_solves.sum()) - solves0,
+                iters=ch.cg_iters.sum(0).cpu().numpy().astype(np.float64) - iters0,
+                accepted=int(ch.n_accept.sum()) - acc0,
+                accepted1=int(ch.n_accept1.sum()) - acc10)
+
+
+def ess_block(trace, wall):
+    from paper_1605_04718_amd import stats
+    summ = stats.summary(trace)
+    ess = [v["ess_bulk"] for v in summ.values()]
+    rh = [v["rhat"] for v in summ.values()]
+    ok = all(math.isfinite(e) for e in ess)
+    return {"min_bulk_ess": min(ess) if ok else None,
+            "max_rhat": max(rh) if all(math.isfinite(r) for r in rh) else None,
+            "ess_per_sec": (min(ess) / wall) if ok and wall > 0 else None,
+            "draws_per_chain": int(trace.shape[0])}
 
 
 def main():
@@ -79,6 +141,10 @@ def main():
     ap.add_argument("--chains", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2000)
+    ap.add_argument("--no-da", action="store_true", help="skip the delayed-acceptance leg")
+    ap.add_argument("--sur-solves", type=int, default=16384,
+                    help="prior solves the surrogate is trained on in the DA leg")
+    ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a known-size kernel that scales "
                          "hardware byte counters)")
@@ -90,8 +156,8 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1605_04718_amd import inputs, stats
-    from paper_1605_04718_amd.api import ChainState, Grid, Problem
+    from paper_1605_04718_amd import inputs
+    from paper_1605_04718_amd.api import DA, PLAIN, ChainState, Grid, Problem
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
@@ -122,50 +188,37 @@ def main():
     cpt = p.autotune()[0]
     log(f"autotuned tile: {cpt} cells per thread ({N_CELLS * N_CELLS // cpt} threads)")
     phi0 = inputs.box_draws(C, LO, HI, seed=inputs.SEED_CHAIN_INIT)
+    phi0_t = torch.tensor(phi0, dtype=torch.float64, device=dev)
     th0 = torch.tensor(inputs.to_natural(phi0), dtype=torch.float64, device=dev)
     ll0, _, _ = p.log_likelihood(th0)
     total = args.warmup + args.steps
-    ch = ChainState.create(torch.tensor(phi0, dtype=torch.float64, device=dev), ll0,
-                           seed=inputs.SEED_SAMPLER, trace_steps=total)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     log(f"setup done: {C} chains, {N_CELLS}^2, {n_steps} IMEX steps per solve")
 
-    with torch.cuda.stream(stream):
-        for k in range(args.warmup):
-            t = time.time()
-            p.mcmc_step(ch, 1)
-            stream.synchronize()
-            log(f"warmup step {k}: {time.time() - t:.2f} s")
-        solves0 = int(ch.n_solves.sum())
-        iters0 = ch.cg_iters.sum(0).cpu().numpy().astype(np.float64)
-        acc0 = int(ch.n_accept.sum())
-        p.solver_timing(enable=True, reset=True)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        for k in range(args.steps):
-            p.mcmc_step(ch, 1)
-            stream.synchronize()
-            log(f"timed step {k}: {time.time() - t0:.2f} s elapsed")
-        torch.cuda.synchronize()
-        wall = time.time() - t0
-    kern_ms, launches = p.solver_timing(enable=False)
-    solves = int(ch.n_solves.sum()) - solves0
-    iters = ch.cg_iters.sum(0).cpu().numpy().astype(np.float64) - iters0
-    accepted = int(ch.n_accept.sum()) - acc0
+    ch = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER,
+                           trace_steps=total)
+    plain = run_leg(p, ch, PLAIN, args.warmup, args.steps, stream, "plain")
+    plain_trace = ch.trace.cpu().numpy()
+
     cells = N_CELLS * N_CELLS
-    cell_steps = solves * cells * n_steps
-    value = cell_steps / wall
+    wall = plain["wall"]
+    solves = plain["solves"]
+    iters = plain["iters"]
+    value = solves * cells * n_steps / wall
     k_u = iters[0] / max(solves * n_steps, 1)
     k_v = iters[1] / max(solves * n_steps, 1)
+    kern_ms = plain["kern_ms"]
     flops = cells * (2 * n_steps * solves * FLOP_SETUP + (iters[0] + iters[1]) * FLOP_CG_ITER)
     achieved = flops / (kern_ms / 1e3) if kern_ms > 0 else 0.0
-    trace = ch.trace.cpu().numpy()
-    summ = stats.summary(trace)
-    ess_vals = [v["ess_bulk"] for v in summ.values()]
-    ess_min = min(ess_vals) if all(math.isfinite(e) for e in ess_vals) else float("nan")
+    ess_plain = ess_block(plain_trace, wall)
+    kernel = f"k_solve_resident<128,{cpt},float>"
+    launches = max(plain["launches"], 1)
+    traffic_per_launch = (MEASURED_TRAFFIC[kernel] * solves * n_steps / launches
+                          if kernel in MEASURED_TRAFFIC else None)
     line = {
-        "metric": "PDE cell-steps/sec (plain batched Metropolis, 128x128); ESS/sec reported beside it",
+        "metric": "PDE cell-steps/sec (plain batched Metropolis, 128x128); ESS/sec and the "
+                  "surrogate delayed-acceptance figures reported beside it",
         "value": value,
         "unit": "cell-steps/s",
         "n_gpus": 1,
@@ -175,26 +228,66 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 fields/CG vectors, f64 dots/misfit/accept",
+        "dtype": "f32 fields (compensated hi+lo) and CG vectors; f64 dots, misfit, accept",
         "data": "synthetic",
         "config": {"workload": "batched plain sampler: 4096 chains, 128x128, T=2 (dt 2.5e-4, 8000 "
-                               "IMEX steps), 4 params, step 2% of prior range",
+                               "IMEX steps), 4 params, step 2% of prior range, chains from prior "
+                               "draws",
                    "chains": C, "grid": N_CELLS, "imex_steps": n_steps, "dt": TAU,
                    "cg_rtol": CG_RTOL, "cg_maxit": CG_MAXIT, "parallelism": "chains on one GPU"},
         "solves": solves,
-        "accept_rate": accepted / max(C * args.steps, 1),
+        "accept_rate": plain["accepted"] / max(C * args.steps, 1),
+        "mh_steps_per_s": C * args.steps / wall,
         "cg_iters_per_step": {"u": k_u, "v": k_v},
         "cell_cg_iters_per_s": cells * (iters[0] + iters[1]) / wall,
-        "ess_per_sec": ess_min / wall if math.isfinite(ess_min) else None,
-        "ess_note": f"min bulk-ESS over (a, b, ln gamma, ln d) of the {total}-step trace of "
-                    f"{C} chains started from prior draws, over the timed wall time; "
-                    f"min bulk-ESS = {ess_min:.1f}",
+        "ess": {"plain": ess_plain,
+                "note": "bulk-ESS (min over a, b, ln gamma, ln d) and split-R-hat of the "
+                        f"{total}-step traces of chains started from prior draws: a transient, "
+                        "not a stationary estimate; ESS/s = min ESS / timed wall time"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
-                     "kernel": f"k_solve_resident<128,{cpt},float>",
-                     "kernel_ms_per_launch": kern_ms / max(launches, 1),
-                     "launches": launches},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": traffic_per_launch,
+                     "traffic_unit": "bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, scaled by "
+                                     "the measured per-solve-step figure of this kernel)",
+                     "kernel": kernel,
+                     "kernel_ms_per_launch": kern_ms / max(plain["launches"], 1),
+                     "launches": plain["launches"],
+                     "flops_per_launch": flops / max(plain["launches"], 1)},
     }
+
+    if not args.no_da:
+        from paper_1605_04718_amd import surrogate
+        p.surrogate_create(512, 4, 32, seed=inputs.SEED_SURROGATE_INIT)
+        t0 = time.time()
+        rep = surrogate.fit(p, sigma, LO, HI, args.sur_solves, args.sur_epochs, log=log)
+        fit_s = time.time() - t0
+        rep.pop("loss_history", None)
+        lls0 = p.surrogate_loglik(phi0_t)
+        torch.cuda.synchronize()
+        chd = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER,
+                                trace_steps=total, da=True)
+        chd.loglik_sur = lls0.clone()
+        da = run_leg(p, chd, DA, args.warmup, args.steps, stream, "da")
+        da_trace = chd.trace.cpu().numpy()
+        dwall = da["wall"]
+        line["da"] = {
+            "cell_steps_per_s": da["solves"] * cells * n_steps / dwall,
+            "ms_per_step": 1e3 * dwall / args.steps,
+            "mh_steps_per_s": C * args.steps / dwall,
+            "mh_steps_speedup_vs_plain": (C * args.steps / dwall) / (C * args.steps / wall),
+            "solves": da["solves"],
+            "solves_per_chain_step": da["solves"] / (C * args.steps),
+            "plain_solves_per_chain_step": solves / (C * args.steps),
+            "stage1_accept_rate": da["accepted1"] / max(C * args.steps, 1),
+            "accept_rate": da["accepted"] / max(C * args.steps, 1),
+            "surrogate": {k: rep[k] for k in ("solves", "dropped", "outliers", "dataset_seconds",
+                                              "train_samples", "epochs", "train_seconds",
+                                              "train_tflops", "final_train_mse", "held_out",
+                                              "sigma1")},
+            "surrogate_fit_seconds": fit_s,
+        }
+        line["ess"]["da"] = ess_block(da_trace, dwall)
+
     if not args.no_cpu_baseline:
         threads = os.cpu_count() or 1
         threads = min(threads, 16)

@@ -683,13 +683,31 @@ extern "C" int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *
     return RD_OK;
 }
 
+// Trial parameters of the autotuner: a fixed low-discrepancy spread over the
+// prior box (the additive recurrence with the plastic-number constants), so
+// that the trial sees the mix of cheap and expensive solves a sampler sees.
+static void trial_theta(const rd_problem_desc &d, int k, double *th)
+{
+    static const double alpha[4] = {0.7548776662466927, 0.5698402909980532, 0.4301597090019468,
+                                    0.2451223337533073};
+    for (int i = 0; i < 4; ++i) {
+        const double f = std::fmod(0.5 + alpha[i] * (k + 1), 1.0);
+        const double x = d.lo[i] + f * (d.hi[i] - d.lo[i]);
+        th[i] = i < 2 ? x : exp(x);
+    }
+}
+
+// A candidate replaces the current tile only when it is faster by more than
+// this fraction (trial timings vary by a few per cent between runs).
+constexpr float kTuneMargin = 0.03f;
+
 extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
 {
     if (!p)
         return fail(RD_EINVAL, "problem is NULL");
     // Trial: one solve per resident workgroup slot over a short horizon, on
     // the homogeneous-state parameters of the prior centre.
-    const int trial_steps = std::min(p->desc.n_steps, 40);
+    const int trial_steps = std::min(p->desc.n_steps, 160);
     for (int g = 0; g < p->desc.n_grids; ++g) {
         const int n = p->grids_host[g].n;
         int best = p->tile[g].cpt;
@@ -700,10 +718,7 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
             const int items = std::min(p->desc.max_batch, p->n_cu * solve_wgs_per_cu(n, p->desc.precision, cpt));
             std::vector<double> th(4 * items);
             for (int k = 0; k < items; ++k) {
-                th[4 * k + 0] = 0.5 * (p->desc.lo[0] + p->desc.hi[0]);
-                th[4 * k + 1] = 0.5 * (p->desc.lo[1] + p->desc.hi[1]);
-                th[4 * k + 2] = exp(0.5 * (p->desc.lo[2] + p->desc.hi[2]));
-                th[4 * k + 3] = exp(0.5 * (p->desc.lo[3] + p->desc.hi[3]));
+                trial_theta(p->desc, k, &th[4 * k]);
             }
             double *d_th = nullptr;
             int *d_st = nullptr;
@@ -742,11 +757,13 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
             if (r != RD_OK)
                 return r;
             // time per item (the slot counts differ between tiles)
-            const float per_item = ms / (float)items;
+            float per_item = ms / (float)items;
             if (getenv("RDBAYES_AUTOTUNE_VERBOSE"))
                 fprintf(stderr, "[rd_autotune] n=%d prec=%d cpt=%d threads=%d wgs/cu=%d: %.4f ms/item\n",
                         n, p->desc.precision, cpt, n * n / cpt,
                         solve_wgs_per_cu(n, p->desc.precision, cpt), per_item);
+            if (cpt == p->tile[g].cpt)
+                per_item *= 1.0f - kTuneMargin;  // incumbent
             if (per_item < best_ms) {
                 best_ms = per_item;
                 best = cpt;
@@ -772,10 +789,7 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
             std::vector<double> th(4 * items);
             std::vector<int> gid(items);
             for (int k = 0; k < items; ++k) {
-                th[4 * k + 0] = 0.5 * (p->desc.lo[0] + p->desc.hi[0]);
-                th[4 * k + 1] = 0.5 * (p->desc.lo[1] + p->desc.hi[1]);
-                th[4 * k + 2] = exp(0.5 * (p->desc.lo[2] + p->desc.hi[2]));
-                th[4 * k + 3] = exp(0.5 * (p->desc.lo[3] + p->desc.hi[3]));
+                trial_theta(p->desc, k, &th[4 * k]);
                 gid[k] = k % p->desc.n_grids;
             }
             double *d_th = nullptr;
@@ -816,10 +830,12 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
             hipFree(d_gid);
             if (r != RD_OK)
                 return r;
-            const float per_item = ms / (float)items;
+            float per_item = ms / (float)items;
             if (getenv("RDBAYES_AUTOTUNE_VERBOSE"))
                 fprintf(stderr, "[rd_autotune] mixed prec=%d threads=%d wgs/cu=%d: %.4f ms/item\n",
                         p->desc.precision, threads, wpc, per_item);
+            if (threads == p->mixed_threads)
+                per_item *= 1.0f - kTuneMargin;  // incumbent
             if (per_item < best_ms) {
                 best_ms = per_item;
                 best = threads;
