@@ -238,6 +238,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             RD_PIN(rr);
         });
     }
+    bool rr_pending = false;
     if (H && pred) {
         __syncthreads();  // every stencil read of P is done
         copy_to_lds<N, R, U, kLds>(H + g.off(), P, g);
@@ -265,11 +266,11 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             r[k] = r[k] - w * q[k];
             RD_GROUP_FENCE(k)
         }
-        // |r0 - w A H|^2 expanded with the rounded w (the elementwise
-        // rounding of r adds a relative 2^-24 per cell at most).
-        const double wd = (double)w;
-        const double rn = rr - 2.0 * wd * rw + wd * wd * ww;
-        rr = uniform(rn > 0.0 ? rn : 0.0);
+        // |r0 - w A H|^2 is not formed by expanding the square: when the
+        // predictor is good the expansion cancels to rounding noise and could
+        // end the solve before it converges.  It is summed from the updated r
+        // in the first CG sweep instead (rr_pending).
+        rr_pending = true;
     } else {
         block_sum2<NW>(bb, rr, red + Slots<NW>::setup);
 #pragma unroll U
@@ -287,15 +288,16 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
     const double tol2 = rtol2 * bb;
     int st = (finite(bb) && finite(rr)) ? 0 : kStNonfinite;
     int it = 0;
-    while (st == 0 && rr > tol2) {
+    while (st == 0 && (rr_pending || rr > tol2)) {
         if (it >= maxit) {
             st = kStNotConverged;
             break;
         }
         __syncthreads();  // p visible to the neighbours
         // Two interleaved FP64 partial sums per dot product halve the
-        // dependent accumulation chains.
-        double pq0 = 0.0, pq1 = 0.0;
+        // dependent accumulation chains.  With rr_pending, p = r here and
+        // the same sweep sums r.r.
+        double pq0 = 0.0, pq1 = 0.0, rp = 0.0;
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
             Real qq = c * t + sigma_at(k) * own;
             RD_PIN(qq);
@@ -307,8 +309,27 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
                 pq0 += (double)own * (double)qq;
                 RD_PIN(pq0);
             }
+            if (rr_pending) {
+                rp += (double)own * (double)own;
+                RD_PIN(rp);
+            }
         });
-        const double pq = block_sum<NW>(pq0 + pq1, red + Slots<NW>::pq);
+        double pq;
+        if (rr_pending) {
+            double v2[2] = {pq0 + pq1, rp};
+            block_sum_n<NW>(v2, red + Slots<NW>::setup);
+            pq = v2[0];
+            rr = v2[1];
+            rr_pending = false;
+            if (!finite(rr)) {
+                st = kStNonfinite;
+                break;
+            }
+            if (!(rr > tol2))
+                break;  // the predictor alone met the tolerance
+        } else {
+            pq = block_sum<NW>(pq0 + pq1, red + Slots<NW>::pq);
+        }
         if (!finite(pq)) {
             st = kStNonfinite;
             break;
