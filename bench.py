@@ -133,6 +133,125 @@ def ess_block(trace, wall):
             "draws_per_chain": int(trace.shape[0])}
 
 
+def laplace_hessian(Problem, Grid, inputs, u0, v0, y, sigma, rtol, h=3e-4):
+    """Central-difference Hessian of Phi at the data-generating parameters
+    (33 misfits in one batched launch): the Laplace approximation the
+    stationary leg sizes its proposal and warm start with."""
+    import itertools
+    import torch
+    n_steps = int(round(T_FINAL / TAU))
+    p = Problem([Grid(n=N_CELLS, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, n_steps, rtol,
+                cg_maxit=2000, lo=LO, hi=HI, max_batch=64)
+    c = inputs.to_sampling(THETA_TRUE)[0]
+    pts = [c.copy()]
+    for i in range(4):
+        for s in (1, -1):
+            q = c.copy()
+            q[i] += s * h
+            pts.append(q)
+    pairs = list(itertools.combinations(range(4), 2))
+    for i, j in pairs:
+        for si, sj in ((1, 1), (1, -1), (-1, 1), (-1, -1)):
+            q = c.copy()
+            q[i] += si * h
+            q[j] += sj * h
+            pts.append(q)
+    ll, st, _ = p.log_likelihood(torch.tensor(inputs.to_natural(np.array(pts)), device="cuda"))
+    torch.cuda.synchronize()
+    ll = ll.cpu().numpy()
+    p.close()
+    H = np.zeros((4, 4))
+    for i in range(4):
+        H[i, i] = (ll[1 + 2 * i] - 2 * ll[0] + ll[2 + 2 * i]) / h ** 2
+    for k, (i, j) in enumerate(pairs):
+        fpp, fpm, fmp, fmm = ll[9 + 4 * k: 13 + 4 * k]
+        H[i, j] = H[j, i] = (fpp - fpm - fmp + fmm) / (4 * h * h)
+    return c, H, float(ll[0])
+
+
+def stationary_leg(args, u0, v0, y, sigma, log):
+    """Plain vs delayed acceptance near stationarity: proposal and warm start
+    from the Laplace approximation, CG tolerance tight enough to resolve the
+    posterior, surrogate trained on draws around it."""
+    import torch
+    from paper_1605_04718_amd import inputs, surrogate
+    from paper_1605_04718_amd.api import DA, PLAIN, ChainState, Grid, Problem
+    n_steps = int(round(T_FINAL / TAU))
+    C, S, rtol = args.st_chains, args.st_steps, args.st_rtol
+    c, H, phi_c = laplace_hessian(Problem, Grid, inputs, u0, v0, y, sigma, rtol)
+    ev = np.linalg.eigvalsh(H)
+    if not ev.min() > 0:
+        raise RuntimeError(f"Laplace Hessian not positive definite: {ev}")
+    cov = np.linalg.inv(H)
+    msd = np.sqrt(np.diag(cov))
+    Lc = np.linalg.cholesky(cov)
+    Lp = np.linalg.cholesky((2.38 ** 2 / 4.0) * cov)   # optimal random-walk scale, d = 4
+    rng = np.random.default_rng(7)
+    phi0 = c + rng.standard_normal((C, 4)) @ Lc.T
+    log(f"stationary: Laplace marginal s.d. {msd}, Phi(theta_true) {phi_c:.1f}")
+    p = Problem([Grid(n=N_CELLS, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, n_steps, rtol,
+                cg_maxit=2000, lo=LO, hi=HI, max_batch=max(C, 4096), prop_chol=Lp)
+    p.autotune()
+    phi0_t = torch.tensor(phi0, dtype=torch.float64, device="cuda")
+    ll0, st0, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"))
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    ch = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER + 10,
+                           trace_steps=S)
+    plain = run_leg(p, ch, PLAIN, 0, S, stream, "stationary plain")
+    tr_p = ch.trace.cpu().numpy()
+    # local surrogate: inputs mapped over +-8 posterior s.d., trained on draws
+    # spread three times wider than the Laplace approximation
+    p.surrogate_create(512, 4, 32, seed=inputs.SEED_SURROGATE_INIT)
+    p.surrogate_set_input_box(c - 8 * msd, c + 8 * msd)
+    draws = c + 3.0 * np.random.default_rng(8).standard_normal((args.st_sur_solves, 4)) @ Lc.T
+    draws = np.clip(draws, c - 8 * msd, c + 8 * msd)
+    t0 = time.time()
+    rep = surrogate.fit(p, sigma, LO, HI, len(draws), args.st_sur_epochs, log=log, phi=draws)
+    fit_s = time.time() - t0
+    lls0 = p.surrogate_loglik(phi0_t)
+    torch.cuda.synchronize()
+    chd = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER + 10,
+                            trace_steps=S, da=True)
+    chd.loglik_sur = lls0.clone()
+    da = run_leg(p, chd, DA, 0, S, stream, "stationary da")
+    tr_d = chd.trace.cpu().numpy()
+    p.close()
+    burn = S // 2
+    from paper_1605_04718_amd import stats
+    sp, sd_ = stats.summary(tr_p[burn:]), stats.summary(tr_d[burn:])
+    agree = {}
+    names = list(sp.keys())
+    for i, k in enumerate(names):
+        se = math.hypot(sp[k]["mcse_mean"], sd_[k]["mcse_mean"])
+        row = {"mean_plain": sp[k]["mean"], "mean_da": sd_[k]["mean"],
+               "mean_diff_in_mcse": abs(sp[k]["mean"] - sd_[k]["mean"]) / se if se > 0 else None}
+        xp, xd = tr_p[burn:, :, i].T, tr_d[burn:, :, i].T
+        for q, nm in ((0.025, "q025"), (0.975, "q975")):
+            qp, qd = float(np.quantile(xp, q)), float(np.quantile(xd, q))
+            sq = math.hypot(stats.mcse_quantile(xp, q), stats.mcse_quantile(xd, q))
+            row[f"{nm}_plain"], row[f"{nm}_da"] = qp, qd
+            row[f"{nm}_diff_in_mcse"] = abs(qp - qd) / sq if sq > 0 else None
+        agree[k] = row
+    ep, ed = ess_block(tr_p[burn:], plain["wall"]), ess_block(tr_d[burn:], da["wall"])
+    return {
+        "workload": f"{C} chains x {S} steps (second half kept), 128x128, T=2, CG rtol {rtol}, "
+                    "correlated random walk with the Laplace covariance x 2.38^2/4, warm start "
+                    "from the Laplace approximation at the data-generating parameters",
+        "laplace_marginal_sd": msd.tolist(),
+        "plain": {"wall_s": plain["wall"], "accept_rate": plain["accepted"] / (C * S),
+                  "solves": plain["solves"], **ep},
+        "da": {"wall_s": da["wall"], "accept_rate": da["accepted"] / (C * S),
+               "stage1_accept_rate": da["accepted1"] / (C * S), "solves": da["solves"],
+               "surrogate_held_out": rep["held_out"], "surrogate_fit_s": fit_s, **ed},
+        "ess_per_sec_speedup": (ed["ess_per_sec"] / ep["ess_per_sec"]
+                                if ed["ess_per_sec"] and ep["ess_per_sec"] else None),
+        "da_ess_per_sec_incl_surrogate_fit": (ed["min_bulk_ess"] / (da["wall"] + fit_s)
+                                              if ed["min_bulk_ess"] else None),
+        "posterior_mean_agreement": agree,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +264,13 @@ def main():
     ap.add_argument("--sur-solves", type=int, default=16384,
                     help="prior solves the surrogate is trained on in the DA leg")
     ap.add_argument("--sur-epochs", type=int, default=40)
+    ap.add_argument("--stationary", action="store_true",
+                    help="also run plain vs delayed acceptance near stationarity (ESS/s)")
+    ap.add_argument("--st-chains", type=int, default=1024)
+    ap.add_argument("--st-steps", type=int, default=40)
+    ap.add_argument("--st-rtol", type=float, default=1e-9)
+    ap.add_argument("--st-sur-solves", type=int, default=8192)
+    ap.add_argument("--st-sur-epochs", type=int, default=60)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a known-size kernel that scales "
                          "hardware byte counters)")
@@ -287,6 +413,9 @@ def main():
             "surrogate_fit_seconds": fit_s,
         }
         line["ess"]["da"] = ess_block(da_trace, dwall)
+
+    if args.stationary:
+        line["stationary"] = stationary_leg(args, u0, v0, y, sigma, log)
 
     if not args.no_cpu_baseline:
         threads = os.cpu_count() or 1

@@ -100,6 +100,13 @@ typedef struct {
     double lo[4], hi[4];           /* uniform prior box in sampling coordinates */
     double step[4];                /* random-walk proposal s.d. per coordinate */
     int32_t max_batch;             /* largest n / n_chains any call will pass */
+    double prop_chol[16];          /* optional lower-triangular proposal factor L
+                                      (row-major [4][4]): when any entry is
+                                      nonzero the random walk is
+                                      phi'_i = phi_i + sum_{j<=i} L[i][j] z_j on
+                                      the free coordinates (a correlated Gaussian
+                                      step, still symmetric) and step[] is not
+                                      used; all zero: phi'_i = phi_i + step_i z_i */
 } rd_problem_desc;
 
 /* Creates a problem: validates the description, uploads the initial fields
@@ -161,9 +168,13 @@ typedef struct {
     uint64_t *n_solves;    /* dev [n] forward solves performed */
     uint64_t *cg_iters;    /* dev [n][2] CG iterations (u, v) summed over those
                               solves, or NULL */
-    double *trace;         /* dev [n_steps][n][4] states after each step, or NULL */
+    double *trace;         /* dev [trace_rows][n][4] states after each step, or NULL:
+                              the step with index s writes row s - trace_step0
+                              (rows outside [0, trace_rows) are not written) */
     uint32_t seed;         /* Philox key word 1 (key word 0 = chain index) */
     uint64_t step;         /* index of the next step; advanced by the calls */
+    uint64_t trace_step0;  /* step index of trace row 0 */
+    int32_t trace_rows;    /* rows the trace holds */
 } rd_chains;
 
 /* n_steps Metropolis-Hastings steps (Sec. 2, Algorithm 1) of every chain.
@@ -180,8 +191,8 @@ typedef struct {
  * iff log U < [Phi(phi) - Phi(phi')] - [Phi~(phi) - Phi~(phi')].
  * On a created stream the steps are replayed from one captured HIP graph per
  * chains layout; on the null stream they are launched directly.
- * chains->step is advanced by n_steps on return (host field).  The trace, if
- * given, must have room for n_steps rows.
+ * chains->step is advanced by n_steps on return (host field).  The trace
+ * keeps one row per step across calls (row = step - trace_step0).
  * Errors: RD_EINVAL (shapes, NULL required arrays), RD_EUNSUPPORTED (DA
  * without a surrogate). */
 int32_t mcmc_step_batch(rd_problem *p, rd_chains *chains, int32_t n_steps, int32_t mode,
@@ -221,6 +232,13 @@ int32_t downsample_batch(rd_problem *p, int32_t n, const void *u, float *out, vo
  * first-stage noise s.d. sigma1 (per pixel). */
 int32_t surrogate_set_scaling(rd_problem *p, const float *mean, const float *sd,
                               double sigma1, void *stream);
+
+/* Box (host double [4] lo < hi, sampling coordinates) over which the
+ * network's inputs are mapped to [-1, 1]; the prior box by default.  A
+ * surrogate trained near the posterior uses a box around it, so that the
+ * small differences between nearby parameters survive the FP32/BF16 input
+ * path.  Set it before training.  Errors: RD_EINVAL. */
+int32_t surrogate_set_input_box(rd_problem *p, const double *lo, const double *hi);
 
 /* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on a batch:
  *   phi dev float64 [batch][4] sampling coordinates

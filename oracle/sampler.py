@@ -35,13 +35,21 @@ PURPOSE_ACCEPT = 1
 PURPOSE_STAGE1 = 2
 
 
-def propose(phi, seed, chain, step, step_sd, free_mask):
-    """phi' = phi + s .* z on the free coordinates (Algorithm 1, first step)."""
+def propose(phi, seed, chain, step, step_sd, free_mask, chol=None):
+    """phi' = phi + s .* z on the free coordinates (Algorithm 1, first step);
+    with a lower-triangular factor L (4 x 4), phi' = phi + L z instead, row i
+    summed over j = 0..i in that order."""
     z = normals4(seed, chain, step, PURPOSE_PROPOSAL)
     prop = np.array(phi, dtype=np.float64).copy()
     for i in range(4):
         if (free_mask >> i) & 1:
-            prop[i] = prop[i] + step_sd[i] * z[i]
+            if chol is not None:
+                dz = 0.0
+                for j in range(i + 1):
+                    dz = dz + float(chol[i][j]) * float(z[j])
+            else:
+                dz = step_sd[i] * z[i]
+            prop[i] = prop[i] + dz
     return prop
 
 

@@ -32,14 +32,15 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("n_grids", c_i32), ("grids", ctypes.POINTER(GridDesc)), ("dt", c_d),
                 ("n_steps", c_i32), ("cg_rtol", c_d), ("cg_maxit", c_i32), ("precision", c_i32),
                 ("free_mask", c_u32), ("lo", c_d * 4), ("hi", c_d * 4), ("step", c_d * 4),
-                ("max_batch", c_i32)]
+                ("max_batch", c_i32), ("prop_chol", c_d * 16)]
 
 
 class Chains(ctypes.Structure):
     _fields_ = [("n_chains", c_i32), ("phi", c_vp), ("loglik", c_vp), ("loglik_sur", c_vp),
                 ("grid_id", c_vp), ("n_accept", c_vp), ("n_accept1", c_vp), ("n_solves", c_vp),
                 ("cg_iters", c_vp),
-                ("trace", c_vp), ("seed", c_u32), ("step", c_u64)]
+                ("trace", c_vp), ("seed", c_u32), ("step", c_u64), ("trace_step0", c_u64),
+                ("trace_rows", c_i32)]
 
 
 SYMBOLS = {
@@ -61,6 +62,7 @@ SYMBOLS = {
     "rd_autotune": (c_i32, [c_vp, c_vp]),
     "rd_solver_timing": (c_i32, [c_vp, c_i32, c_dp, ctypes.POINTER(c_i64), c_i32]),
     "rd_mixed_threads": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),
+    "surrogate_set_input_box": (c_i32, [c_vp, c_dp, c_dp]),
     "rd_status_string": (ctypes.c_char_p, [c_i32]),
     "rd_last_error": (ctypes.c_char_p, []),
 }

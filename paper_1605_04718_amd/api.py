@@ -51,7 +51,9 @@ class Problem:
 
     def __init__(self, grids, dt, n_steps, cg_rtol, *, precision=FP32, cg_maxit=0,
                  free_mask=0b1111, lo=(0, 0, 0, 0), hi=(1, 1, 1, 1), step=(0, 0, 0, 0),
-                 max_batch=4096):
+                 max_batch=4096, prop_chol=None):
+        """prop_chol: optional lower-triangular 4 x 4 factor L of a correlated
+        random-walk step (phi' = phi + L z); step is then unused."""
         if isinstance(grids, Grid):
             grids = [grids]
         self.grids = list(grids)
@@ -91,6 +93,11 @@ class Problem:
         for i in range(4):
             d.lo[i], d.hi[i], d.step[i] = lo[i], hi[i], step[i]
         d.max_batch = max_batch
+        if prop_chol is not None:
+            L = np.asarray(prop_chol, dtype=np.float64).reshape(4, 4)
+            for i in range(4):
+                for j in range(4):
+                    d.prop_chol[4 * i + j] = L[i, j]
         h = ctypes.c_void_p()
         torch.cuda.init()
         check(lib().init_problem(ctypes.byref(d), ctypes.byref(h)), "init_problem")
@@ -186,6 +193,11 @@ class Problem:
               "downsample_batch")
         return out
 
+    def surrogate_set_input_box(self, lo, hi):
+        lo_a = (ctypes.c_double * 4)(*[float(x) for x in lo])
+        hi_a = (ctypes.c_double * 4)(*[float(x) for x in hi])
+        check(lib().surrogate_set_input_box(self.h, lo_a, hi_a), "surrogate_set_input_box")
+
     def surrogate_set_scaling(self, mean, sd, sigma1, stream=None):
         check(lib().surrogate_set_scaling(self.h, _ptr(mean), _ptr(sd), float(sigma1),
                                           _stream(stream)), "surrogate_set_scaling")
@@ -261,6 +273,7 @@ class ChainState:
     n_solves: torch.Tensor | None = None
     cg_iters: torch.Tensor | None = None
     trace: torch.Tensor | None = None
+    trace_step0: int = 0
 
     @property
     def n(self):
@@ -276,7 +289,7 @@ class ChainState:
                    grid_id=grid_id, n_accept=z(), n_accept1=z(), n_solves=z(),
                    cg_iters=torch.zeros((n, 2), dtype=torch.int64, device=dev),
                    trace=(torch.zeros((trace_steps, n, 4), dtype=torch.float64, device=dev)
-                          if trace_steps else None))
+                          if trace_steps else None), trace_step0=step)
 
     def struct(self) -> Chains:
         c = Chains()
@@ -290,6 +303,8 @@ class ChainState:
         c.n_solves = _ptr(self.n_solves)
         c.cg_iters = _ptr(self.cg_iters)
         c.trace = _ptr(self.trace)
+        c.trace_rows = self.trace.shape[0] if self.trace is not None else 0
+        c.trace_step0 = self.trace_step0
         c.seed = self.seed
         c.step = self.step
         return c

@@ -245,6 +245,8 @@ int32_t check_chains(rd_problem *p, const rd_chains *c, int mode)
                     p->desc.max_batch);
     if (!c->phi || !c->loglik)
         return fail(RD_EINVAL, "chains->phi and chains->loglik are required");
+    if (c->trace && c->trace_rows < 0)
+        return fail(RD_EINVAL, "chains->trace_rows < 0");
     if (mode == RD_MODE_DA && !c->loglik_sur)
         return fail(RD_EINVAL, "delayed acceptance needs chains->loglik_sur");
     return RD_OK;
@@ -257,6 +259,12 @@ SamplerArgs sampler_args(rd_problem *p, const rd_chains *c)
     a.seed = c->seed;
     a.ctr = p->ctr;
     a.cfg.free_mask = p->desc.free_mask;
+    a.cfg.use_chol = 0;
+    for (int i = 0; i < 16; ++i) {
+        a.cfg.chol[i] = p->desc.prop_chol[i];
+        if (p->desc.prop_chol[i] != 0.0)
+            a.cfg.use_chol = 1;
+    }
     for (int i = 0; i < 4; ++i) {
         a.cfg.lo[i] = p->desc.lo[i];
         a.cfg.hi[i] = p->desc.hi[i];
@@ -277,6 +285,7 @@ SamplerArgs sampler_args(rd_problem *p, const rd_chains *c)
     a.cg_iters = c->cg_iters;
     a.iters = p->iters_ws;
     a.trace = c->trace;
+    a.trace_rows = c->trace ? c->trace_rows : 0;
     return a;
 }
 
@@ -310,8 +319,7 @@ bool same_chains(const rd_chains &a, const rd_chains &b)
     return a.n_chains == b.n_chains && a.phi == b.phi && a.loglik == b.loglik &&
            a.loglik_sur == b.loglik_sur && a.grid_id == b.grid_id && a.n_accept == b.n_accept &&
            a.n_accept1 == b.n_accept1 && a.n_solves == b.n_solves && a.cg_iters == b.cg_iters &&
-           a.trace == b.trace &&
-           a.seed == b.seed;
+           a.trace == b.trace && a.trace_rows == b.trace_rows && a.seed == b.seed;
 }
 
 void drop_graphs(rd_problem *p)
@@ -347,6 +355,10 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     for (int i = 0; i < 4; ++i)
         if (!(desc->lo[i] <= desc->hi[i]) || !(desc->step[i] >= 0.0))
             return fail(RD_EINVAL, "prior box / step of coordinate %d invalid", i);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            if ((j > i && desc->prop_chol[4 * i + j] != 0.0) || !std::isfinite(desc->prop_chol[4 * i + j]))
+                return fail(RD_EINVAL, "prop_chol must be finite and lower-triangular");
     for (int g = 0; g < desc->n_grids; ++g) {
         const rd_grid_desc &gd = desc->grids[g];
         if (!tile_supported(gd.n, desc->precision, default_cpt(gd.n, desc->precision)))
@@ -584,7 +596,7 @@ extern "C" int32_t mcmc_step_batch(rd_problem *p, rd_chains *chains, int32_t n_s
         return RD_OK;
     }
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->step, s));
+    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->trace_step0, s));
     // Graph capture needs a created stream (the legacy null stream cannot
     // be captured); the null stream and timing runs use direct launches.
     const bool graphs = p->use_graphs && !p->timing && s != nullptr;
@@ -652,7 +664,7 @@ extern "C" int32_t propose_batch(rd_problem *p, rd_chains *chains, double *phi_p
     if (!phi_prop || !inside)
         return fail(RD_EINVAL, "phi_prop and inside are required");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->step, s));
+    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->trace_step0, s));
     SamplerArgs a = sampler_args(p, chains);
     a.phi_prop = phi_prop;
     a.inside = inside;
@@ -672,7 +684,7 @@ extern "C" int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *
     if (!phi_prop || !inside || !loglik_prop)
         return fail(RD_EINVAL, "phi_prop, inside and loglik_prop are required");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->step, s));
+    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->trace_step0, s));
     SamplerArgs a = sampler_args(p, chains);
     a.phi_prop = const_cast<double *>(phi_prop);
     a.inside = const_cast<int *>(inside);
@@ -966,6 +978,20 @@ extern "C" int32_t surrogate_set_scaling(rd_problem *p, const float *mean, const
     if (!p->grids_host[0].y)
         return fail(RD_EINVAL, "grid 0 has no data y");
     HIP_TRY(surrogate_scaling(p->sur, mean, sd, sigma1, (hipStream_t)stream));
+    drop_graphs(p);
+    return RD_OK;
+}
+
+extern "C" int32_t surrogate_set_input_box(rd_problem *p, const double *lo, const double *hi)
+{
+    if (!p || !p->sur)
+        return fail(RD_EINVAL, "surrogate_set_input_box needs surrogate_create first");
+    if (!lo || !hi)
+        return fail(RD_EINVAL, "lo and hi are required");
+    for (int i = 0; i < 4; ++i)
+        if (!(lo[i] < hi[i]) || !std::isfinite(lo[i]) || !std::isfinite(hi[i]))
+            return fail(RD_EINVAL, "input box coordinate %d: need finite lo < hi", i);
+    surrogate_input_box(p->sur, lo, hi);
     drop_graphs(p);
     return RD_OK;
 }

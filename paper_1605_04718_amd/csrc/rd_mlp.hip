@@ -466,6 +466,16 @@ hipError_t surrogate_downsample(Surrogate *s, int n, const void *u, float *out, 
     return hipGetLastError();
 }
 
+// Box of the sampling coordinates that the network's inputs are mapped to
+// [-1, 1] over (the prior box by default).
+void surrogate_input_box(Surrogate *s, const double lo[4], const double hi[4])
+{
+    for (int i = 0; i < 4; ++i) {
+        s->d.lo[i] = lo[i];
+        s->d.hi[i] = hi[i];
+    }
+}
+
 hipError_t surrogate_scaling(Surrogate *s, const float *mean, const float *sd, double sigma1,
                              hipStream_t st)
 {

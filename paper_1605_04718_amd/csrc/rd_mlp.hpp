@@ -28,6 +28,7 @@ bool surrogate_ready(const Surrogate *s);
 int surrogate_max_batch(const Surrogate *s);
 int surrogate_layers(const Surrogate *s);
 hipError_t surrogate_downsample(Surrogate *s, int n, const void *u, float *out, hipStream_t st);
+void surrogate_input_box(Surrogate *s, const double lo[4], const double hi[4]);
 hipError_t surrogate_scaling(Surrogate *s, const float *mean, const float *sd, double sigma1,
                              hipStream_t st);
 hipError_t surrogate_train(Surrogate *s, int batch, const double *phi, const float *target,

@@ -13,7 +13,8 @@ namespace rd {
 
 enum : uint32_t { kPurposeProposal = 0, kPurposeAccept = 1, kPurposeStage1 = 2 };
 
-// phi' = phi + s .* z (free coordinates), z ~ N(0, I); inside = every
+// phi' = phi + s .* z, or phi + L z with the proposal factor (free
+// coordinates), z ~ N(0, I); inside = every
 // coordinate within [lo, hi]; theta' = (a, b, exp(ln gamma), exp(ln d)).
 __global__ void k_propose(SamplerArgs a)
 {
@@ -29,8 +30,17 @@ __global__ void k_propose(SamplerArgs a)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         p[i] = a.phi[4 * c + i];
-        if ((a.cfg.free_mask >> i) & 1u)
-            p[i] = p[i] + a.cfg.step[i] * z[i];
+        if ((a.cfg.free_mask >> i) & 1u) {
+            double dz = 0.0;
+            if (a.cfg.use_chol) {
+                // row i of L z, summed in column order
+                for (int j = 0; j <= i; ++j)
+                    dz = dz + a.cfg.chol[4 * i + j] * z[j];
+            } else {
+                dz = a.cfg.step[i] * z[i];
+            }
+            p[i] = p[i] + dz;
+        }
         in = in && (a.cfg.lo[i] <= p[i]) && (p[i] <= a.cfg.hi[i]);
         a.phi_prop[4 * c + i] = p[i];
     }
@@ -70,7 +80,7 @@ __global__ void k_accept(SamplerArgs a)
         if (a.n_accept)
             a.n_accept[c] += 1;
     }
-    if (a.trace) {
+    if (a.trace && step >= a.ctr[1] && step - a.ctr[1] < (uint64_t)a.trace_rows) {
         const uint64_t row = step - a.ctr[1];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -126,7 +136,7 @@ __global__ void k_da_stage2(SamplerArgs a)
         if (a.n_accept)
             a.n_accept[c] += 1;
     }
-    if (a.trace) {
+    if (a.trace && step >= a.ctr[1] && step - a.ctr[1] < (uint64_t)a.trace_rows) {
         const uint64_t row = step - a.ctr[1];
 #pragma unroll
         for (int i = 0; i < 4; ++i)

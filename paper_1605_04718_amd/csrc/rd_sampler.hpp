@@ -7,7 +7,9 @@ namespace rd {
 
 struct SamplerCfg {
     uint32_t free_mask;
+    int use_chol;          // proposal step L z instead of step .* z
     double lo[4], hi[4], step[4];
+    double chol[16];       // lower-triangular L, row-major
 };
 
 struct SamplerArgs {
@@ -29,7 +31,8 @@ struct SamplerArgs {
     uint64_t *n_solves;
     uint64_t *cg_iters;           // [n][2] accumulated CG iterations or null
     const int *iters;             // [n][2] CG iterations of this step's solves
-    double *trace;                // [rows][n][4] or null
+    double *trace;                // [rows][n][4] or null; row = step - ctr[1]
+    int trace_rows;
 };
 
 hipError_t launch_propose(const SamplerArgs &a, hipStream_t s);

@@ -46,16 +46,20 @@ class Dataset:
 
 
 def make_dataset(p, m, lo, hi, seed=inputs.SEED_DATASET, batch=4096, max_abs=10.0,
-                 log=None) -> Dataset:
+                 log=None, phi=None) -> Dataset:
     """m prior draws (uniform on the box [lo, hi] in sampling coordinates),
     each solved to T on grid class 0 and downsampled to the surrogate's
     output size.  Failed solves are dropped, and so are fields with a block
     mean above max_abs in magnitude: at the largest gamma of the box the
     time step leaves the stable range of the linearised scheme for some
     (a, b), and the resulting large spurious fields would dominate a
-    squared-error fit while lying far from any posterior mass."""
+    squared-error fit while lying far from any posterior mass.  `phi`
+    ([m, 4]) replaces the prior draws, e.g. draws around the posterior."""
     dev = torch.device("cuda")
-    phi_all = torch.tensor(inputs.box_draws(m, lo, hi, seed=seed), dtype=torch.float64, device=dev)
+    if phi is None:
+        phi = inputs.box_draws(m, lo, hi, seed=seed)
+    phi_all = torch.as_tensor(np.asarray(phi), dtype=torch.float64).to(dev)
+    m = phi_all.shape[0]
     S = p.sur_shape[2]
     keep_phi, keep_u = [], []
     dropped = outliers = 0
@@ -162,10 +166,11 @@ def first_stage_sigma(sigma, block, rms):
     return math.sqrt(sigma * sigma / block + rms * rms)
 
 
-def fit(p, sigma, lo, hi, solves, epochs, batch=1024, lr=1e-3, held_out=0.05, log=None):
+def fit(p, sigma, lo, hi, solves, epochs, batch=1024, lr=1e-3, held_out=0.05, log=None,
+        phi=None):
     """Dataset -> split -> standardisation -> training -> held-out error ->
     first-stage scaling installed in p.  Returns a report dict."""
-    ds = make_dataset(p, solves, lo, hi, log=log)
+    ds = make_dataset(p, solves, lo, hi, log=log, phi=phi)
     (ph_tr, u_tr), (ph_te, u_te) = split(ds, held_out)
     mean, sd = standardisation(u_tr)
     target = ((u_tr - mean) / sd).float().contiguous()

@@ -44,6 +44,31 @@ def test_proposals_match_oracle_stream():
     p.close()
 
 
+def test_correlated_proposals_match_oracle_stream():
+    """The proposal with a lower-triangular factor L (phi' = phi + L z)."""
+    import torch
+    from paper_1605_04718_amd.api import Grid, Problem
+    need_gpu()
+    C = 200
+    L = np.array([[0.02, 0, 0, 0], [-0.01, 0.015, 0, 0], [0.003, 0.004, 0.05, 0],
+                  [0.03, -0.02, 0.01, 0.04]])
+    u0, v0 = inputs.initial_fields(32, 0.1, 0.9)
+    p = Problem([Grid(n=32, u0=u0, v0=v0)], TAU, 1, 1e-7, lo=LO, hi=HI, free_mask=0b1011,
+                max_batch=C, prop_chol=L)
+    phi = inputs.box_draws(C, LO, HI, seed=9)
+    ch = chains_at(phi, np.zeros(C), seed=77)
+    ch.step = 12345
+    prop, inside = p.propose(ch)
+    torch.cuda.synchronize()
+    prop, inside = prop.cpu().numpy(), inside.cpu().numpy()
+    for c in range(C):
+        want = osamp.propose(phi[c], 77, c, 12345, None, 0b1011, chol=L)
+        assert np.allclose(prop[c], want, rtol=1e-14, atol=1e-14)
+        assert prop[c][2] == phi[c][2]          # fixed coordinate untouched
+        assert bool(inside[c]) == osamp.in_box(want, LO, HI)
+    p.close()
+
+
 def test_accept_decisions_match_oracle_bitwise():
     import torch
     need_gpu()
@@ -147,6 +172,29 @@ def test_mcmc_step_on_pde_matches_oracle_chain():
     assert np.allclose(ch.loglik.cpu().numpy(), lls, rtol=1e-8)
     assert np.allclose(ch.trace.cpu().numpy(), np.stack(trace), rtol=1e-12, atol=1e-13)
     assert ch.step == S
+    p.close()
+
+
+def test_trace_rows_across_calls():
+    """One call of S steps and S calls of one step fill the same trace rows."""
+    import torch
+    need_gpu()
+    S = 3
+    p, phi0, ll_fn, step = _pde_chain_setup()
+    ll0 = ll_fn(phi0)
+    a = chains_at(phi0, ll0, seed=5, trace_steps=S)
+    p.mcmc_step(a, S)
+    b = chains_at(phi0, ll0, seed=5, trace_steps=S)
+    for _ in range(S):
+        p.mcmc_step(b, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a.trace, b.trace) and torch.equal(a.phi, b.phi)
+    assert torch.equal(b.trace[-1], b.phi)
+    # a trace that ran out of rows is left alone (no write past its end)
+    c = chains_at(phi0, ll0, seed=5, trace_steps=1)
+    p.mcmc_step(c, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(c.trace[0], a.trace[0])
     p.close()
 
 

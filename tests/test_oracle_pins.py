@@ -434,3 +434,21 @@ def test_da_with_exact_surrogate_never_rejects_at_stage_two_and_constant_is_plai
                                                lambda q: 0.0)
         assert a1
         assert np.array_equal(pa, pb) and lla == llb
+
+
+def test_correlated_proposal_reduces_to_diagonal_and_has_covariance_LLt():
+    """phi' = phi + L z: a diagonal L gives the per-coordinate step exactly,
+    and the empirical covariance of the steps of a general L is L L^T."""
+    step = np.array([0.3, 0.02, 0.5, 0.07])
+    phi = np.array([0.2, 0.4, 5.0, 2.0])
+    for s in range(20):
+        a = osamp.propose(phi, 9, 3, s, step, 0b1111)
+        b = osamp.propose(phi, 9, 3, s, None, 0b1111, chol=np.diag(step))
+        assert np.array_equal(a, b)
+    L = np.array([[1.0, 0, 0, 0], [0.5, 0.8, 0, 0], [-0.3, 0.2, 0.6, 0], [0.1, -0.4, 0.3, 0.5]])
+    d = np.array([osamp.propose(np.zeros(4), 11, 0, s, None, 0b1111, chol=L) for s in range(20000)])
+    assert np.allclose(d.mean(axis=0), 0.0, atol=0.03)
+    assert np.allclose(np.cov(d.T), L @ L.T, atol=0.04)
+    # fixed coordinates do not move
+    e = osamp.propose(phi, 11, 0, 0, None, 0b0101, chol=L)
+    assert e[1] == phi[1] and e[3] == phi[3]
