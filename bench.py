@@ -46,15 +46,17 @@ HI = (1.0, 1.0, math.log(500.0), math.log(50.0))
 CG_RTOL = 1e-7
 CG_MAXIT = 400
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed); FLOP/s
-# Algorithmic FP operations of the fused solve (per cell, per species):
-#   one CG iteration: 5-point differences (7), reaction diagonal (2),
-#   q = sigma p + c t (2), p.q (2), r -= alpha q (1), r.r (2),
-#   d += alpha p (1), p = r + beta p (1) -> 18
+# Algorithmic FP operations of the fused solve (per cell, per species; a
+# fused multiply-add counts 2):
+#   one CG iteration: q = A p (5-point differences 7, c t + sigma p 3), the
+#   two dot products of CG (4) and its three vector updates (6) -> 20; the
+#   kernel's extra work (re-forming the diagonal, the third dot product that
+#   saves a reduction) is not counted
 #   one step's set-up: residual of the high part (14: differences 7,
 #   diagonal 2, residual 2, right-hand side 1, its norm 2), of the low part
 #   (14) and the compensated fold of the increment (10) -> 38 (the optional
 #   predictor sweep is not counted)
-FLOP_CG_ITER = 18.0
+FLOP_CG_ITER = 20.0
 FLOP_SETUP = 38.0
 # HBM bytes of the fused solve kernel from two rocprofv3 PMC passes over the
 # timed step of `bench.py --steps 1 --warmup 0 --no-da --no-cpu-baseline`
@@ -252,6 +254,80 @@ def stationary_leg(args, u0, v0, y, sigma, log):
     }
 
 
+def mixed_leg(args, log):
+    """The uneven workload: chains split 4:2:1 over 64^2, 128^2 and 256^2
+    grids, half on stationary and half on growing domains (rho = e^{0.01 t}),
+    six datasets, one persistent launch per step, the step replayed from a
+    captured graph; wall-clock cell-steps/s of the solves performed."""
+    import torch
+    from paper_1605_04718_amd import inputs
+    from paper_1605_04718_amd.api import ChainState, Grid, Problem
+    n_steps = int(round(T_FINAL / TAU))
+    classes = [(64, 0), (64, 1), (128, 0), (128, 1), (256, 0), (256, 1)]
+    counts = {64: 2340, 128: 1170, 256: 585}
+    grids = []
+    for n, growth in classes:
+        u0, v0 = inputs.initial_fields(n, THETA_TRUE[0], THETA_TRUE[1])
+        grids.append((n, growth, u0, v0))
+    # data: each class's own noise-free field at theta_true from the library
+    gen = Problem([Grid(n=n, u0=u0, v0=v0, growth=g, growth_rate=0.01 if g else 0.0)
+                   for n, g, u0, v0 in grids], TAU, n_steps, CG_RTOL, cg_maxit=CG_MAXIT,
+                  max_batch=len(classes))
+    th = torch.tensor([THETA_TRUE] * len(classes), dtype=torch.float64, device="cuda")
+    gid = torch.arange(len(classes), dtype=torch.int32, device="cuda")
+    ut, _, st, _ = gen.forward_solve(th, grid_id=gid)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    gen.close()
+    gl = []
+    for k, (n, g, u0, v0) in enumerate(grids):
+        y, sigma = inputs.noisy_data(ut[k, :n * n].double().cpu().numpy().reshape(n, n), 0.01,
+                                     seed=100 + k)
+        gl.append(Grid(n=n, u0=u0, v0=v0, y=y, sigma=sigma, growth=g,
+                       growth_rate=0.01 if g else 0.0))
+    ids = []
+    for k, (n, g, _, _) in enumerate(grids):
+        ids += [k] * (counts[n] // 2 + (counts[n] % 2 if g == 0 else 0))
+    C = len(ids)
+    ids = torch.tensor(np.array(ids, dtype=np.int32), device="cuda")
+    step = tuple(0.02 * (h - l) for l, h in zip(LO, HI))
+    p = Problem(gl, TAU, n_steps, CG_RTOL, cg_maxit=CG_MAXIT, lo=LO, hi=HI, step=step,
+                max_batch=C)
+    p.autotune()
+    T = p.mixed_threads()
+    phi0 = inputs.box_draws(C, LO, HI, seed=inputs.SEED_CHAIN_INIT)
+    ll0, _, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"), grid_id=ids)
+    ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0, seed=inputs.SEED_SAMPLER,
+                           grid_id=ids)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        # warm-up: the first step of a new layout runs directly, the second is
+        # captured; the timed steps are graph replays
+        p.mcmc_step(ch, max(2, args.warmup))
+        stream.synchronize()
+        per_class0 = ch.n_solves.cpu().numpy().copy()
+        t0 = time.time()
+        p.mcmc_step(ch, args.steps)
+        stream.synchronize()
+        wall = time.time() - t0
+    solves = ch.n_solves.cpu().numpy() - per_class0
+    idn = ids.cpu().numpy()
+    cell_steps = 0.0
+    per = {}
+    for k, (n, g, _, _) in enumerate(grids):
+        sk = int(solves[idn == k].sum())
+        per[f"{n}{'g' if g else 's'}"] = sk
+        cell_steps += sk * n * n * n_steps
+    p.close()
+    log(f"mixed: {C} chains, workgroup {T} threads, {args.steps} steps in {wall:.2f} s")
+    return {"workload": f"{C} chains: 2340 x 64^2, 1170 x 128^2, 585 x 256^2, half stationary and "
+                        "half growing (rho = exp(0.01 t)), 6 datasets, T=2, one persistent launch "
+                        "per step replayed from a captured graph",
+            "cell_steps_per_s": cell_steps / wall, "ms_per_step": 1e3 * wall / args.steps,
+            "mixed_threads": T, "solves_per_class": per}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +340,8 @@ def main():
     ap.add_argument("--sur-solves", type=int, default=16384,
                     help="prior solves the surrogate is trained on in the DA leg")
     ap.add_argument("--sur-epochs", type=int, default=40)
+    ap.add_argument("--mixed", action="store_true",
+                    help="also run the uneven 64/128/256 workload in one persistent launch")
     ap.add_argument("--stationary", action="store_true",
                     help="also run plain vs delayed acceptance near stationarity (ESS/s)")
     ap.add_argument("--st-chains", type=int, default=1024)
@@ -414,6 +492,8 @@ def main():
         }
         line["ess"]["da"] = ess_block(da_trace, dwall)
 
+    if args.mixed:
+        line["mixed"] = mixed_leg(args, log)
     if args.stationary:
         line["stationary"] = stationary_leg(args, u0, v0, y, sigma, log)
 

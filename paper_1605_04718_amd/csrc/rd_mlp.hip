@@ -179,29 +179,60 @@ __global__ void k_layer0_fwd(int npad, int width, const float *x, const float *W
     h[i] = (bf16)gelu_f(s);
 }
 
+// Reductions over the batch rows (weight gradient of the first layer, bias
+// gradients): a block takes 64 columns, its 16 waves take every 16th row,
+// and the 16 partial sums are added in a fixed order (deterministic).
+constexpr int kRowGroups = 16;
+
 // First layer weight gradient: gW[n][k] = sum_r dz[r][n] x[r][k].
-__global__ void k_layer0_wgrad(int rows, int width, const float *x, const float *dz, float *gW)
+__global__ __launch_bounds__(1024) void k_layer0_wgrad(int rows, int width, const float *x,
+                                                       const float *dz, float *gW)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= width * 4)
-        return;
-    const int n = i >> 2, k = i & 3;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r)
-        s = fmaf(dz[(size_t)r * width + n], x[r * 4 + k], s);
-    gW[i] = s;
+    __shared__ float part[kRowGroups][64][4];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    if (n < width) {
+        for (int r = grp; r < rows; r += kRowGroups) {
+            const float d = dz[(size_t)r * width + n];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                s[k] = fmaf(d, x[r * 4 + k], s[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        part[grp][lane][k] = s[k];
+    __syncthreads();
+    if (grp == 0 && n < width) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float t = 0.f;
+            for (int q = 0; q < kRowGroups; ++q)
+                t += part[q][lane][k];
+            gW[n * 4 + k] = t;
+        }
+    }
 }
 
 // Column sums (bias gradient): db[n] = sum_r dz[r][n].
-__global__ void k_colsum(int rows, int cols, const float *dz, float *db)
+__global__ __launch_bounds__(1024) void k_colsum(int rows, int cols, const float *dz, float *db)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= cols)
-        return;
+    __shared__ float part[kRowGroups][64];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int r = 0; r < rows; ++r)
-        s += dz[(size_t)r * cols + n];
-    db[n] = s;
+    if (n < cols)
+        for (int r = grp; r < rows; r += kRowGroups)
+            s += dz[(size_t)r * cols + n];
+    part[grp][lane] = s;
+    __syncthreads();
+    if (grp == 0 && n < cols) {
+        float t = 0.f;
+        for (int q = 0; q < kRowGroups; ++q)
+            t += part[q][lane];
+        db[n] = t;
+    }
 }
 
 // MSE over `rows` x cols: dy = 2 (y - t) / (rows cols) (zero on padded rows),
@@ -552,7 +583,7 @@ hipError_t surrogate_train(Surrogate *s, int batch, const double *phi, const flo
         gw.c32 = s->gW[l];
         if ((e = gemm<true, true, kEpiStore>(gw, st)) != hipSuccess)
             break;
-        hipLaunchKernelGGL(k_colsum, blocks_for(s->dout[l]), dim3(256), 0, st, mp, s->dout[l],
+        hipLaunchKernelGGL(k_colsum, dim3((s->dout[l] + 63) / 64), dim3(1024), 0, st, mp, s->dout[l],
                            s->dz32[cur], s->gb[l]);
         // input gradient times GELU'(z_{l-1}): dz_{l-1} = (dz W) .* GELU'(z)
         GemmArgs gi{};
@@ -572,9 +603,9 @@ hipError_t surrogate_train(Surrogate *s, int batch, const double *phi, const flo
     }
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_layer0_wgrad, blocks_for((size_t)s->dout[0] * 4), dim3(256), 0, st, mp,
+    hipLaunchKernelGGL(k_layer0_wgrad, dim3((s->dout[0] + 63) / 64), dim3(1024), 0, st, mp,
                        s->dout[0], s->x0, s->dz32[cur], s->gW[0]);
-    hipLaunchKernelGGL(k_colsum, blocks_for(s->dout[0]), dim3(256), 0, st, mp, s->dout[0],
+    hipLaunchKernelGGL(k_colsum, dim3((s->dout[0] + 63) / 64), dim3(1024), 0, st, mp, s->dout[0],
                        s->dz32[cur], s->gb[0]);
     s->t += 1;
     for (int l = 0; l < s->L; ++l) {
