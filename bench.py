@@ -264,7 +264,8 @@ def mixed_leg(args, log):
     from paper_1605_04718_amd.api import ChainState, Grid, Problem
     n_steps = int(round(T_FINAL / TAU))
     classes = [(64, 0), (64, 1), (128, 0), (128, 1), (256, 0), (256, 1)]
-    counts = {64: 2340, 128: 1170, 256: 585}
+    counts = {n: max(2, int(round(c * args.mixed_scale)))
+              for n, c in ((64, 2340), (128, 1170), (256, 585))}
     grids = []
     for n, growth in classes:
         u0, v0 = inputs.initial_fields(n, THETA_TRUE[0], THETA_TRUE[1])
@@ -275,6 +276,7 @@ def mixed_leg(args, log):
                   max_batch=len(classes))
     th = torch.tensor([THETA_TRUE] * len(classes), dtype=torch.float64, device="cuda")
     gid = torch.arange(len(classes), dtype=torch.int32, device="cuda")
+    log("mixed: data solves (one per class)")
     ut, _, st, _ = gen.forward_solve(th, grid_id=gid)
     torch.cuda.synchronize()
     assert int(st.abs().sum()) == 0
@@ -295,8 +297,11 @@ def mixed_leg(args, log):
                 max_batch=C)
     p.autotune()
     T = p.mixed_threads()
+    log(f"mixed: autotuned workgroup {T} threads; initial misfits of {C} chains")
     phi0 = inputs.box_draws(C, LO, HI, seed=inputs.SEED_CHAIN_INIT)
     ll0, _, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"), grid_id=ids)
+    torch.cuda.synchronize()
+    log("mixed: initial misfits done")
     ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0, seed=inputs.SEED_SAMPLER,
                            grid_id=ids)
     stream = torch.cuda.Stream()
@@ -304,12 +309,16 @@ def mixed_leg(args, log):
     with torch.cuda.stream(stream):
         # warm-up: the first step of a new layout runs directly, the second is
         # captured; the timed steps are graph replays
-        p.mcmc_step(ch, max(2, args.warmup))
+        t = time.time()
+        p.mcmc_step(ch, 2)
         stream.synchronize()
+        log(f"mixed warmup (2 steps, the second captured): {time.time() - t:.1f} s")
         per_class0 = ch.n_solves.cpu().numpy().copy()
         t0 = time.time()
-        p.mcmc_step(ch, args.steps)
-        stream.synchronize()
+        for k in range(args.steps):
+            p.mcmc_step(ch, 1)
+            stream.synchronize()
+            log(f"mixed timed step {k}: {time.time() - t0:.1f} s elapsed")
         wall = time.time() - t0
     solves = ch.n_solves.cpu().numpy() - per_class0
     idn = ids.cpu().numpy()
@@ -321,9 +330,10 @@ def mixed_leg(args, log):
         cell_steps += sk * n * n * n_steps
     p.close()
     log(f"mixed: {C} chains, workgroup {T} threads, {args.steps} steps in {wall:.2f} s")
-    return {"workload": f"{C} chains: 2340 x 64^2, 1170 x 128^2, 585 x 256^2, half stationary and "
-                        "half growing (rho = exp(0.01 t)), 6 datasets, T=2, one persistent launch "
-                        "per step replayed from a captured graph",
+    return {"workload": f"{C} chains: {counts[64]} x 64^2, {counts[128]} x 128^2, "
+                        f"{counts[256]} x 256^2 (the 4:2:1 mix at {args.mixed_scale:g} of 4095 "
+                        "chains), half stationary and half growing (rho = exp(0.01 t)), 6 datasets, "
+                        "T=2, one persistent launch per step replayed from a captured graph",
             "cell_steps_per_s": cell_steps / wall, "ms_per_step": 1e3 * wall / args.steps,
             "mixed_threads": T, "solves_per_class": per}
 
@@ -342,6 +352,8 @@ def main():
     ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--mixed", action="store_true",
                     help="also run the uneven 64/128/256 workload in one persistent launch")
+    ap.add_argument("--mixed-scale", type=float, default=1.0,
+                    help="fraction of the 4095 chains of the uneven workload")
     ap.add_argument("--stationary", action="store_true",
                     help="also run plain vs delayed acceptance near stationarity (ESS/s)")
     ap.add_argument("--st-chains", type=int, default=1024)
