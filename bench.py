@@ -257,7 +257,8 @@ def stationary_leg(args, u0, v0, y, sigma, log):
 def mixed_leg(args, log):
     """The uneven workload: chains split 4:2:1 over 64^2, 128^2 and 256^2
     grids, half on stationary and half on growing domains (rho = e^{0.01 t}),
-    six datasets, one persistent launch per step, the step replayed from a
+    six datasets; per step a cooperative launch for the 256^2 items and a
+    persistent launch for the other classes, the step replayed from a
     captured graph; wall-clock cell-steps/s of the solves performed."""
     import torch
     from paper_1605_04718_amd import inputs
@@ -333,7 +334,8 @@ def mixed_leg(args, log):
     return {"workload": f"{C} chains: {counts[64]} x 64^2, {counts[128]} x 128^2, "
                         f"{counts[256]} x 256^2 (the 4:2:1 mix at {args.mixed_scale:g} of 4095 "
                         "chains), half stationary and half growing (rho = exp(0.01 t)), 6 datasets, "
-                        "T=2, one persistent launch per step replayed from a captured graph",
+                        "T=2, per step a cooperative launch for the 256^2 items and a "
+                        "persistent launch for the rest, replayed from a captured graph",
             "cell_steps_per_s": cell_steps / wall, "ms_per_step": 1e3 * wall / args.steps,
             "mixed_threads": T, "solves_per_class": per}
 

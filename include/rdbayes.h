@@ -275,6 +275,15 @@ int32_t surrogate_params(rd_problem *p, int32_t layer, float *w, float *b, int32
  * choice is cached per device, grid size and precision for later problems. */
 int32_t rd_autotune(rd_problem *p, int32_t *cpt_out);
 
+/* Selects the tile of grid class `grid` by its cells per thread (the value
+ * rd_autotune reports), overriding the default and any cached choice for
+ * this problem only.  Supported values depend on the grid size and
+ * precision; at 256 x 256 in FP32, cpt = 16 selects the cooperative tile
+ * (four workgroups share an item, each holding a 64-row strip resident).
+ * Errors: RD_EINVAL (NULL problem, grid out of range), RD_EUNSUPPORTED (no
+ * kernel for that cpt at this size and precision). */
+int32_t rd_set_tile(rd_problem *p, int32_t grid, int32_t cpt);
+
 /* Workgroup size of the launch that serves batches mixing grid classes
  * (host int32 out).  Errors: RD_EINVAL (NULL argument). */
 int32_t rd_mixed_threads(const rd_problem *p, int32_t *threads);

@@ -245,6 +245,10 @@ class Problem:
         check(lib().rd_autotune(self.h, ctypes.cast(out, ctypes.c_void_p)), "rd_autotune")
         return list(out)
 
+    def set_tile(self, grid, cpt):
+        """Select grid class `grid`'s tile by cells per thread."""
+        check(lib().rd_set_tile(self.h, int(grid), int(cpt)), "rd_set_tile")
+
     def mixed_threads(self):
         """Workgroup size of the launch that serves batches mixing grid classes."""
         t = ctypes.c_int32()

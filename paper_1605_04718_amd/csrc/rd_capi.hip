@@ -93,6 +93,9 @@ struct rd_problem {
     void *gws = nullptr;     // per-workgroup solve slots
     size_t gws_stride = 0;
     int gws_slots = 0;
+    void *coop = nullptr;    // cooperative-solve workspace (256^2 FP32)
+    int coop_groups = 0;
+    int coop_wpc = 0;        // resident cooperative workgroups per CU
     // timing of the fused solve kernel
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -215,12 +218,24 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     a.gws = p->gws;
     a.gws_stride = p->gws_stride;
     a.gws_slots = p->gws_slots;
+    a.coop = p->coop;
+    a.coop_groups = p->coop_groups;
     const TileChoice t = p->tile[g];
     // wgs_per_cu was queried when the tile was chosen: no runtime query may
     // run here, since this is also called while a stream is being captured.
     int wgs = p->n_cu * (mixed ? p->mixed_wpc : p->wgs_per_cu[g]);
-    if (wgs > n)
+    // (a cooperative tile sizes its grid from the item count itself)
+    if (wgs > n && (mixed || !tile_coop(nn, p->desc.precision, t.cpt)))
         wgs = n;
+    // batches mixing classes: a cooperative launch first serves the 256^2
+    // FP32 items (the prefix of the class-ordered queue) in groups of four
+    // workgroups, then the mixed launch serves the other classes
+    a.coop_wgs = 0;
+    int coop_grid = 0;
+    if (mixed && p->coop && p->desc.precision == 0) {
+        coop_grid = std::min(p->n_cu * p->coop_wpc / 32 * 32, p->coop_groups * kCoopG);
+        a.coop_wgs = coop_grid >= 32 ? coop_grid : 0;
+    }
     HIP_TRY(launch_fill_u32(p->queue, 0u, 1, s));
     if (mixed) {
         HIP_TRY(launch_class_order(grid_id, n, p->desc.n_grids, p->rank, p->order_ws, s));
@@ -228,6 +243,8 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     }
     hipEvent_t e0;
     HIP_TRY(record_solve_start(p, s, &e0));
+    if (mixed && a.coop_wgs)
+        HIP_TRY(launch_solve_coop(a, coop_grid, s));
     if (mixed)
         HIP_TRY(launch_solve_mixed(p->desc.precision, p->mixed_threads, a, wgs, s));
     else
@@ -485,6 +502,17 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         p->mixed_wpc = mixed_wgs_per_cu(desc->precision, p->mixed_threads);
         p->order_ws = (int *)dmalloc(p, sizeof(int) * desc->max_batch, &err);
     }
+    // cooperative tiles: group counters, partial sums and edge rows
+    for (int g = 0; g < desc->n_grids; ++g) {
+        const int n = p->grids_host[g].n;
+        for (int cpt : {4, 8, 16, 32, 64, 128}) {
+            if (tile_coop(n, desc->precision, cpt) && !p->coop) {
+                p->coop_wpc = solve_wgs_per_cu(n, desc->precision, cpt);
+                p->coop_groups = p->n_cu * p->coop_wpc / kCoopG + 8;
+                p->coop = dmalloc(p, coop_workspace_bytes(p->coop_groups), &err);
+            }
+        }
+    }
     slot = (slot + 255) / 256 * 256;
     p->gws = dmalloc(p, slot * (size_t)slots, &err);
     p->gws_stride = slot;
@@ -725,9 +753,13 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
         int best = p->tile[g].cpt;
         float best_ms = 1e30f;
         for (int cpt : {4, 8, 16, 32, 64, 128}) {
-            if (!tile_supported(n, p->desc.precision, cpt) || n * n / cpt > 1024 || n * n / cpt < 64)
+            const bool coop = tile_coop(n, p->desc.precision, cpt);
+            if (!tile_supported(n, p->desc.precision, cpt) ||
+                (!coop && (n * n / cpt > 1024 || n * n / cpt < 64)))
                 continue;
-            const int items = std::min(p->desc.max_batch, p->n_cu * solve_wgs_per_cu(n, p->desc.precision, cpt));
+            int items = std::min(p->desc.max_batch, p->n_cu * solve_wgs_per_cu(n, p->desc.precision, cpt));
+            if (coop)  // a group of workgroups per item
+                items = std::max(1, items / kCoopG);
             std::vector<double> th(4 * items);
             for (int k = 0; k < items; ++k) {
                 trial_theta(p->desc, k, &th[4 * k]);
@@ -861,6 +893,21 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
         }
     }
     drop_graphs(p);
+    return RD_OK;
+}
+
+extern "C" int32_t rd_set_tile(rd_problem *p, int32_t grid, int32_t cpt)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    if (grid < 0 || grid >= p->desc.n_grids)
+        return fail(RD_EINVAL, "grid %d outside [0, %d)", grid, p->desc.n_grids);
+    const int n = p->grids_host[grid].n;
+    if (cpt <= 0 || !tile_supported(n, p->desc.precision, cpt))
+        return fail(RD_EUNSUPPORTED, "no tile with %d cells per thread at n = %d", cpt, n);
+    // the workspace was sized for every supported tile of this class
+    p->tile[grid] = TileChoice{cpt, n * n / cpt};
+    p->wgs_per_cu[grid] = solve_wgs_per_cu(n, p->desc.precision, cpt);
     return RD_OK;
 }
 

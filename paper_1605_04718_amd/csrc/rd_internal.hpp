@@ -53,7 +53,20 @@ struct SolveArgs {
                              // streamed strip arrays)
     size_t gws_stride;       // bytes per slot
     int gws_slots;           // number of slots
+    void *coop;              // cooperative-solve workspace (per group: partial sums
+                             // and edge rows), or null
+    int coop_groups;         // groups the workspace holds
+    int coop_wgs;            // class-ordered batch: nonzero when a cooperative
+                             // launch serves the 256^2 items (the mixed launch
+                             // then skips them)
 };
+
+// Cooperative solve of one large grid by a group of workgroups.
+constexpr int kCoopN = 256;       // grid size served this way
+constexpr int kCoopG = 4;         // workgroups per item (horizontal strips of 64 rows)
+constexpr int kCoopThreads = 1024;
+__host__ __device__ size_t coop_workspace_bytes(int groups);
+hipError_t launch_solve_coop(const SolveArgs &a, int grid_wgs, hipStream_t s);
 
 // Class ranks of a mixed batch (queue order: rank 0 first).
 constexpr int kMaxClasses = 8;
@@ -75,6 +88,7 @@ hipError_t launch_solve_mixed(int precision, int threads, const SolveArgs &a, in
 hipError_t launch_class_order(const int *grid_id, int n, int n_grids, const RankTable &rank,
                               int *order, hipStream_t s);
 bool mixed_supported(int n, int precision, int threads);
+bool tile_coop(int n, int precision, int cpt);  // a group of workgroups per item
 size_t mixed_slot_bytes(int n, int precision, int threads);
 int mixed_wgs_per_cu(int precision, int threads);
 bool tile_supported(int n, int precision, int cpt);

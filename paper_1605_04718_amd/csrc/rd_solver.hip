@@ -735,34 +735,6 @@ __device__ __forceinline__ void solve_item_class(const SolveArgs &a, int c, cons
     }
 }
 
-template <int T, typename Real>
-__global__ __launch_bounds__(T) void k_solve_mixed(SolveArgs a)
-{
-    constexpr int NW = T / kWave;
-    constexpr int NM = MixedTraits<Real>::kMaxResident;
-    __shared__ Real P[NM * NM];
-    __shared__ Real stash[NM * NM];
-    __shared__ double red[Slots<NW>::total];
-    __shared__ int s_item;
-    Real *slot = (Real *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
-    for (int item = next_item(a.queue, &s_item); item < a.n_items;
-         item = next_item(a.queue, &s_item)) {
-        const int c = uniform(a.order ? a.order[item] : item);
-        const int gid = (!a.need || uniform(a.need[c])) ? item_grid(a, c) : -1;
-        if (gid >= 0) {
-            const GridDev &gd = a.grids[gid];
-            const int n = uniform(gd.n);
-            if (n == 32)
-                solve_item_class<32, T, Real>(a, c, gd, P, stash, red, slot);
-            else if (n == 64)
-                solve_item_class<64, T, Real>(a, c, gd, P, stash, red, slot);
-            else if (n == 128)
-                solve_item_class<128, T, Real>(a, c, gd, P, stash, red, slot);
-            else if (n == 256)
-                solve_item_class<256, T, Real>(a, c, gd, P, stash, red, slot);
-        }
-    }
-}
 
 // Queue order of a mixed batch: the stable counting sort of the items by
 // grid class in the order `rank` (rank[g] = position of class g, most costly
@@ -804,6 +776,769 @@ __global__ __launch_bounds__(1024) void k_class_order(const int *grid_id, int n,
         order[local[class_rank(rank, grid_id[i], n_grids)]++] = i;
 }
 
+// ---------------------------------------------------------------------------
+// Cooperative solve of a large grid (256 x 256) by a group of G workgroups.
+//
+// A single workgroup cannot hold a 256^2 item in VGPRs and LDS, and the
+// streamed variant (arrays in HBM) takes ~30 s per solve on one CU.  Here
+// member m of the group owns the horizontal strip of rows 64m .. 64m+63 and
+// keeps it resident exactly as the 128^2 kernel does (16 cells per thread,
+// 1024 threads); the 5-point stencil needs the neighbouring members' edge
+// rows, and CG's dot products need the group's sums.  Both go through a
+// per-group area of global memory with agent-coherent (sc1) loads and
+// stores.  A group exchange publishes each member's partial sums tagged
+// with the exchange's sequence number and polls the other members' slots
+// until their tags match; it doubles as the group barrier, since a member
+// publishes only after its own edge-row stores have completed.  No cache
+// flush or invalidate is involved, so other workgroups' cached data is left
+// alone.  The members of a group get workgroup ids that are congruent
+// modulo 8, which the dispatcher places on the same XCD.
+//
+// Edge rows travel one iteration ahead: a member publishes its new residual
+// edge rows before the r.r reduction, and after it computes the neighbours'
+// new search-direction edge rows itself, p_nb = r_nb + beta p_nb, so one CG
+// iteration needs two group exchanges (p.q and r.r).  A member rewrites an
+// exchange buffer or an edge row only after an exchange that every member
+// entered after its last read of it.
+
+constexpr int kCoopStrip = kCoopN / kCoopG;              // 64 rows per member
+constexpr int kCoopR = kCoopStrip * kCoopN / kCoopThreads;  // 16 cells per thread
+// A group barrier gives up after this many ticks of the 100 MHz real-time
+// counter (10 s): far beyond any legitimate wait, it only bounds the damage
+// of a member that can never arrive.
+constexpr unsigned long long kCoopWaitTicks = 1000000000ull;
+
+struct CoopArea {
+    // header: the item queue; then per group: partial sums [2][G][4]
+    // doubles, then edge rows [4 fields][G][2][N]
+    static constexpr size_t header_bytes = 256;
+    static constexpr size_t partial_bytes = 2 * kCoopG * 4 * sizeof(double);
+    static constexpr size_t group_bytes =
+        partial_bytes + (size_t)4 * kCoopG * 2 * kCoopN * sizeof(float);
+};
+
+__host__ __device__ size_t coop_workspace_bytes(int groups)
+{
+    return CoopArea::header_bytes + (size_t)groups * CoopArea::group_bytes;
+}
+
+enum CoopField : int { kFieldHi = 0, kFieldLo = 1, kFieldH = 2, kFieldR = 3 };
+
+struct CoopCtx {
+    unsigned char *base;  // the group's area
+    int m;                // member index
+    unsigned seq;         // exchanges so far (this launch)
+    int *fail;            // LDS flag: an exchange timed out
+    double *gather;       // LDS [G * 4]
+
+    __device__ double *partial(unsigned k) const
+    {
+        return (double *)base + (size_t)(k & 1u) * kCoopG * 4;
+    }
+    __device__ float *halo_row(int field, int member, int side) const
+    {
+        return (float *)(base + CoopArea::partial_bytes) +
+               (((size_t)field * kCoopG + member) * 2 + side) * kCoopN;
+    }
+};
+
+// Per-lane offset made opaque at its use: the address is formed next to the
+// access from the uniform base, instead of a 64-bit lane address hoisted out
+// of the CG loop (which the register allocator then spills).
+__device__ __forceinline__ int lane_off(int o)
+{
+    asm volatile("" : "+v"(o));
+    return o;
+}
+
+__device__ __forceinline__ void coop_store(float *p, float v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float coop_load(const float *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void coop_store(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double coop_load(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A published value carries the exchange's sequence number in its 8 lowest
+// mantissa bits, so the value is its own arrival flag: one coherent store
+// and one poll per member, no counter.  The change is below 2^-44 relative,
+// far under the rounding error of the FP64 sums themselves, and every
+// member sums the same tagged values in the same order.  Exchanges are
+// double buffered by sequence parity; a buffer's stale tag is two behind.
+__device__ __forceinline__ double with_tag(double v, unsigned tag)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return __longlong_as_double((long long)((b & ~0xFFull) | (tag & 0xFFu)));
+}
+__device__ __forceinline__ unsigned tag_of(double v)
+{
+    return (unsigned)((unsigned long long)__double_as_longlong(v) & 0xFFu);
+}
+
+// Group exchange of M values that every thread of the member holds: on
+// return v holds the sums over the members, in member order (the same in
+// every member).  Also a group barrier: every coherent store that a thread
+// of any member issued before the exchange is visible after it.  Bounded:
+// after kCoopWaitTicks the member gives up and raises *fail, and a member
+// that has failed no longer waits, so every exchange ends.
+template <int M>
+__device__ void coop_exchange(double (&v)[M], CoopCtx &x)
+{
+    // this thread's coherent stores are complete before the value is published
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    x.seq += 1;
+    const unsigned tag = x.seq & 0xFFu;
+    double *buf = x.partial(x.seq);
+    const int t = threadIdx.x;
+    if (t < kCoopG * M) {
+        const int mm = t / M, j = t % M;  // lane t: value j of member mm
+        double mine = v[0];
+#pragma unroll
+        for (int q = 1; q < M; ++q)
+            if (j == q)
+                mine = v[q];
+        double got = with_tag(mine, tag);
+        // The store and the polls are separate blocks, store first: as the
+        // two sides of one branch they could run in either order within
+        // the wave, and a wave that polls before it stores waits for
+        // members that do the same.
+        if (mm == x.m)
+            coop_store(buf + lane_off(x.m * 4 + j), got);
+        asm volatile("" ::: "memory");
+        if (mm != x.m && !*x.fail) {
+            got = coop_load(buf + lane_off(mm * 4 + j));
+            if (tag_of(got) != tag) {
+                const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+                do {
+                    __builtin_amdgcn_s_sleep(1);
+                    got = coop_load(buf + lane_off(mm * 4 + j));
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > kCoopWaitTicks) {
+                        *x.fail = 1;
+                        break;
+                    }
+                } while (tag_of(got) != tag);
+            }
+        }
+        x.gather[t] = got;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < kCoopG; ++mm)
+            sum += x.gather[mm * M + j];
+        v[j] = uniform(sum);
+    }
+}
+
+// Group barrier (an exchange of nothing).
+__device__ __forceinline__ void coop_sync(CoopCtx &x)
+{
+    double z[1] = {0.0};
+    coop_exchange<1>(z, x);
+}
+
+// Sums of M per-thread values over the group's threads.
+template <int NW, int M>
+__device__ __forceinline__ void coop_sum(double (&v)[M], double *red, CoopCtx &x)
+{
+    block_sum_n<NW>(v, red);
+    coop_exchange<M>(v, x);
+}
+
+// Thread layout of a member: thread t owns column i = t % N, local rows
+// jl0 .. jl0 + R - 1 of the strip.  LDS P has one halo row on each side:
+// local row jl is at P[(jl + 1) N + i].
+struct CoopGeo {
+    int i, jl0, iw, ie;
+    __device__ CoopGeo()
+    {
+        i = threadIdx.x % kCoopN;
+        jl0 = (threadIdx.x / kCoopN) * kCoopR;
+        iw = i > 0 ? i - 1 : i;
+        ie = i < kCoopN - 1 ? i + 1 : i;
+    }
+    __device__ int idx(int k) const { return (jl0 + k + 1) * kCoopN + i; }  // into P (halo rows)
+    __device__ int sidx(int k) const { return (jl0 + k) * kCoopN + i; }     // strip arrays
+    __device__ __forceinline__ int off() const
+    {
+        int o = jl0 * kCoopN + i;
+        asm volatile("" : "+v"(o));
+        return o;
+    }
+    __device__ bool top() const { return jl0 == 0; }                           // owns row 0
+    __device__ bool bottom() const { return jl0 + kCoopR == kCoopStrip; }      // owns last row
+};
+
+// 5-point sweep over own cells with the halo rows in place.
+template <typename F>
+__device__ __forceinline__ void sweep_coop(const float *P, const CoopGeo &g, F &&f)
+{
+    constexpr int N = kCoopN, R = kCoopR;
+    float cur = P[g.idx(0)];
+    float south = P[g.idx(0) - N];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const float north = P[g.idx(k) + N];
+        const float west = P[g.idx(k) - g.i + g.iw];
+        const float east = P[g.idx(k) - g.i + g.ie];
+        const float t = ((cur - west) + (cur - east)) + ((cur - south) + (cur - north));
+        f(k, cur, t);
+        south = cur;
+        cur = north;
+        RD_GROUP_FENCE(k)
+    }
+}
+
+// Publish this member's edge rows of `field` (values v(k) of own cells).
+template <class V>
+__device__ __forceinline__ void coop_publish(const CoopCtx &x, int field, const CoopGeo &g, V &&v)
+{
+    if (g.top())
+        coop_store(x.halo_row(field, x.m, 0) + lane_off(g.i), v(0));
+    if (g.bottom())
+        coop_store(x.halo_row(field, x.m, 1) + lane_off(g.i), v(kCoopR - 1));
+}
+
+// After a barrier: fill P's halo rows with the neighbours' published edge
+// rows of `field` (mirror rows at the domain boundary: the member's own
+// edge row, already in P).  The caller synchronises before the sweep.
+__device__ __forceinline__ void coop_fetch_halo(const CoopCtx &x, int field, float *P)
+{
+    constexpr int N = kCoopN;
+    const int t = threadIdx.x;
+    if (t < N) {
+        P[t] = x.m > 0 ? coop_load(x.halo_row(field, x.m - 1, 1) + lane_off(t)) : P[N + t];
+    } else if (t < 2 * N) {
+        const int c = t - N;
+        P[(kCoopStrip + 1) * N + c] = x.m < kCoopG - 1
+                                          ? coop_load(x.halo_row(field, x.m + 1, 0) + lane_off(c))
+                                          : P[kCoopStrip * N + c];
+    }
+}
+
+// CG for the increment of one species on the member's strip (the algorithm
+// of cg_solve, FP32 compensated, with group barriers for halos and sums).
+template <int kSp>
+__device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoopN> &S,
+                       RegArr<float, kCoopR> &r, RegArr<float, kCoopR> &q,
+                       RegArr<float, kCoopR> &d, float inv_dt, float c, float src, float dl,
+                       float gam, double rtol2, int maxit, float *P, const float *lo,
+                       const float *H, bool pred, double *red, const CoopGeo &g, CoopCtx &x,
+                       int &it_acc)
+{
+    constexpr int R = kCoopR, NW = kCoopThreads / kWave;
+    const float e0 = uniform(kSp == 0 ? dl + gam : dl);
+    const float s0 = uniform(e0 + inv_dt);
+    auto e_at = [&](int k) -> float {
+        if constexpr (kSp == 0)
+            return e0 - gam * (hi[k] * S[k]);
+        else
+            return e0 + gam * (S[k] * S[k]);
+    };
+    auto sigma_at = [&](int k) -> float {
+        if constexpr (kSp == 0)
+            return s0 - gam * (hi[k] * S[k]);
+        else
+            return s0 + gam * (S[k] * S[k]);
+    };
+    const float *lp = lo + g.off();
+    const float *hp = H + g.off();
+    // every field of the set-up travels before one barrier
+    coop_publish(x, kFieldHi, g, [&](int k) { return hi[k]; });
+    coop_publish(x, kFieldLo, g, [&](int k) { return lp[k * kCoopN]; });
+    if (pred)
+        coop_publish(x, kFieldH, g, [&](int k) { return hp[k * kCoopN]; });
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        P[g.idx(k)] = hi[k];
+        RD_GROUP_FENCE(k)
+    }
+    coop_sync(x);
+    coop_fetch_halo(x, kFieldHi, P);
+    __syncthreads();
+    double bb = 0.0, rr = 0.0;
+    sweep_coop(P, g, [&](int k, float own, float t) {
+        const float b = own * inv_dt + src;
+        float res = src - e_at(k) * own - c * t;
+        RD_PIN(res);
+        r[k] = res;
+        bb += (double)b * (double)b;
+        RD_PIN(bb);
+    });
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        P[g.idx(k)] = lp[k * kCoopN];
+    __syncthreads();
+    coop_fetch_halo(x, kFieldLo, P);
+    __syncthreads();
+    sweep_coop(P, g, [&](int k, float own, float t) {
+        float res = r[k] - (e_at(k) * own + c * t);
+        RD_PIN(res);
+        r[k] = res;
+        rr += (double)res * (double)res;
+        RD_PIN(rr);
+    });
+    bool rr_pending = false;
+    if (pred) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            P[g.idx(k)] = hp[k * kCoopN];
+        __syncthreads();
+        coop_fetch_halo(x, kFieldH, P);
+        __syncthreads();
+        double rw = 0.0, ww = 0.0;
+        sweep_coop(P, g, [&](int k, float own, float t) {
+            float w = c * t + sigma_at(k) * own;
+            RD_PIN(w);
+            q[k] = w;
+            rw += (double)r[k] * (double)w;
+            ww += (double)w * (double)w;
+            RD_PIN(rw);
+            RD_PIN(ww);
+        });
+        double v4[4] = {bb, rr, rw, ww};
+        coop_sum<NW>(v4, red, x);
+        bb = v4[0];
+        rw = v4[2];
+        ww = v4[3];
+        const float w = uniform((float)((ww > 0.0 && finite(rw)) ? rw / ww : 0.0));
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            d[k] = w * P[g.idx(k)];
+            r[k] = r[k] - w * q[k];
+            RD_GROUP_FENCE(k)
+        }
+        rr_pending = true;  // |r|^2 is summed exactly in the first CG sweep
+        // the halo of p = r (the predicted residual) comes from the
+        // neighbours' own update: exchanged below with the r rows
+    } else {
+        double v2[2] = {bb, rr};
+        coop_sum<NW>(v2, red, x);
+        bb = v2[0];
+        rr = v2[1];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            d[k] = 0.0f;
+    }
+    // p0 = r: own rows, and the neighbours' edge rows of r
+    coop_publish(x, kFieldR, g, [&](int k) { return r[k]; });
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        P[g.idx(k)] = r[k];
+        RD_GROUP_FENCE(k)
+    }
+    coop_sync(x);
+    coop_fetch_halo(x, kFieldR, P);
+
+    const double tol2 = rtol2 * bb;
+    int st = (finite(bb) && finite(rr)) ? 0 : kStNonfinite;
+    int it = 0;
+    while (st == 0 && (rr_pending || rr > tol2)) {
+        if (*x.fail) {
+            st = kStNotConverged;
+            break;
+        }
+        if (it >= maxit) {
+            st = kStNotConverged;
+            break;
+        }
+        __syncthreads();  // p (own rows and halo) visible
+        double pq = 0.0, rp = 0.0;
+        sweep_coop(P, g, [&](int k, float own, float t) {
+            float qq = c * t + sigma_at(k) * own;
+            RD_PIN(qq);
+            q[k] = qq;
+            pq += (double)own * (double)qq;
+            RD_PIN(pq);
+            if (rr_pending) {
+                rp += (double)own * (double)own;
+                RD_PIN(rp);
+            }
+        });
+        double v2[2] = {pq, rp};
+        coop_sum<NW>(v2, red, x);
+        pq = v2[0];
+        if (rr_pending) {
+            rr = v2[1];
+            rr_pending = false;
+            if (!finite(rr)) {
+                st = kStNonfinite;
+                break;
+            }
+            if (!(rr > tol2))
+                break;
+        }
+        if (!finite(pq)) {
+            st = kStNonfinite;
+            break;
+        }
+        if (!(pq > 0.0)) {
+            st = kStBreakdown;
+            break;
+        }
+        const float a = uniform((float)(rr / pq));
+        double rn = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float v = r[k] - a * q[k];
+            r[k] = v;
+            rn += (double)v * (double)v;
+            RD_GROUP_FENCE(k)
+        }
+        coop_publish(x, kFieldR, g, [&](int k) { return r[k]; });
+        double v1[1] = {rn};
+        coop_sum<NW>(v1, red, x);
+        rn = v1[0];
+        ++it;
+        if (!finite(rn)) {
+            st = kStNonfinite;
+            break;
+        }
+        const float bt = uniform((float)(rn / rr));
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float p = P[g.idx(k)];
+            d[k] = d[k] + a * p;
+            P[g.idx(k)] = __builtin_fmaf(bt, p, r[k]);
+            RD_GROUP_FENCE(k)
+        }
+        // neighbours' new edge rows of p from their published r and the old p
+        {
+            constexpr int N = kCoopN;
+            const int t = threadIdx.x;
+            if (t < N && x.m > 0) {
+                P[t] = __builtin_fmaf(bt, P[t],
+                                      coop_load(x.halo_row(kFieldR, x.m - 1, 1) + lane_off(t)));
+            } else if (t >= N && t < 2 * N && x.m < kCoopG - 1) {
+                float *h = P + (kCoopStrip + 1) * N + (t - N);
+                *h = __builtin_fmaf(bt, *h,
+                                    coop_load(x.halo_row(kFieldR, x.m + 1, 0) + lane_off(t - N)));
+            }
+        }
+        __syncthreads();
+        // mirror rows at the domain boundary follow the member's own edge rows
+        {
+            constexpr int N = kCoopN;
+            const int t = threadIdx.x;
+            if (t < N && x.m == 0)
+                P[t] = P[N + t];
+            else if (t >= N && t < 2 * N && x.m == kCoopG - 1)
+                P[(kCoopStrip + 1) * N + t - N] = P[kCoopStrip * N + t - N];
+        }
+        rr = rn;
+    }
+    if (*x.fail)
+        st |= kStNotConverged;
+    it_acc += it;
+    __syncthreads();
+    return st;
+}
+
+// fold for the member's strip (same arithmetic as fold()).
+template <bool kDGlobal>
+__device__ __forceinline__ void fold_coop(RegArr<float, kCoopR> &hi, RegArr<float, kCoopR> &d,
+                                          float *lo, float *H, const CoopGeo &g)
+{
+    const int o = g.off();
+    float l[kCoopR], dd[kCoopR];
+#pragma unroll
+    for (int k = 0; k < kCoopR; ++k) {
+        l[k] = lo[o + k * kCoopN];
+        dd[k] = kDGlobal ? H[o + k * kCoopN] : d[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kCoopR; ++k) {
+        RD_PIN(l[k]);
+        RD_PIN(dd[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < kCoopR; ++k) {
+        float s, e;
+        two_sum(hi[k], dd[k], s, e);
+        const float lk = l[k] + e;
+        const float nh = s + lk;
+        hi[k] = nh;
+        lo[o + k * kCoopN] = lk - (nh - s);
+        if (!kDGlobal)
+            H[o + k * kCoopN] = dd[k];
+    }
+}
+
+// One 256^2 item by the group.  Mirrors integrate() + finish_item().
+__device__ void solve_item_coop(const SolveArgs &a, int c, const GridDev &gd, float *P,
+                                float *stash, double *red, float *slot, CoopCtx &x)
+{
+    constexpr int N = kCoopN, R = kCoopR, NS = kCoopStrip, NW = kCoopThreads / kWave;
+    constexpr size_t strip = (size_t)NS * N;
+    const CoopGeo g;
+    const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
+                          a.theta[4 * c + 3]};
+    float *lo_u = slot, *lo_v = slot + strip, *h_u = slot + 2 * strip, *h_v = slot + 3 * strip;
+    RegArr<float, R> xu, xv, r, q, d;
+    {
+        const int o = g.off();
+        const size_t base = (size_t)x.m * strip;  // the member's rows of the whole field
+        const float *u0 = (const float *)gd.u0 + base + o;
+        const float *v0 = (const float *)gd.v0 + base + o;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            xu[k] = u0[k * N];
+            xv[k] = v0[k * N];
+            lo_u[o + k * N] = u0[(size_t)N * N + k * N];
+            lo_v[o + k * N] = v0[(size_t)N * N + k * N];
+        }
+    }
+    const float inv_dt = uniform((float)(1.0 / a.dt));
+    const float gam = uniform((float)th[2]);
+    const float src_u = uniform((float)(th[2] * th[0]));
+    const float src_v = uniform((float)(th[2] * th[1]));
+    const float dl = uniform((float)gd.dil);
+    const double n2 = (double)N * (double)N;
+    const double decay = gd.decay;
+    double rho_m2 = 1.0;
+    int st = 0, itu = 0, itv = 0, last_u = 0, last_v = 0;
+    LdsArr<float, N> sv{stash + g.sidx(0)};
+    for (int s = 0; s < a.n_steps; ++s, rho_m2 = uniform(rho_m2 * decay)) {
+        const float cu = uniform((float)(rho_m2 * n2));
+        const float cv = uniform((float)(th[3] * rho_m2 * n2));
+        const bool pred_u = s > 0 && last_u > 0, pred_v = s > 0 && last_v > 0;
+        const int itu0 = itu, itv0 = itv;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            sv[k] = xv[k];
+        st = cg_coop<0>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam, a.rtol2, a.maxit, P, lo_u,
+                        h_u, pred_u, red, g, x, itu);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            xv[k] = sv[k];
+            if (!st)
+                sv[k] = xu[k];
+        }
+        if (st)
+            break;
+        {
+            const int o = g.off();
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                h_u[o + k * N] = d[k];
+        }
+        st = cg_coop<1>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam, a.rtol2, a.maxit, P, lo_v,
+                        h_v, pred_v, red, g, x, itv);
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            xu[k] = sv[k];
+        if (st)
+            break;
+        fold_coop<false>(xv, d, lo_v, h_v, g);
+        fold_coop<true>(xu, d, lo_u, h_u, g);
+        last_u = uniform(itu - itu0);
+        last_v = uniform(itv - itv0);
+    }
+    // outputs: each member writes its rows; misfit summed over the group
+    const size_t off = (size_t)c * a.out_stride + (size_t)x.m * strip;
+    const int o = g.off();
+    if (a.u_out) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            ((float *)a.u_out)[off + o + k * N] = xu[k];
+    }
+    if (a.v_out) {
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            ((float *)a.v_out)[off + o + k * N] = xv[k];
+    }
+    if (a.phi) {
+        double sum = 0.0;
+        if (gd.y) {
+            const double *y = gd.y + (size_t)x.m * strip + o;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const double e = y[k * N] - ((double)xu[k] + (double)lo_u[o + k * N]);
+                sum += e * e;
+            }
+        }
+        double v1[1] = {sum};
+        coop_sum<NW>(v1, red, x);
+        if (threadIdx.x == 0 && x.m == 0)
+            a.phi[c] = (st != 0 || !gd.y || !finite(v1[0])) ? __builtin_inf() : v1[0] * gd.inv_2s2;
+    }
+    if (threadIdx.x == 0 && x.m == 0) {
+        a.status[c] = st;
+        if (a.iters) {
+            a.iters[2 * c] = itu;
+            a.iters[2 * c + 1] = itv;
+        }
+    }
+}
+
+// Marks queue items failed, starting with the one in *s_item, until the
+// queue (or, with prefix_only, its 256^2 prefix) is exhausted.
+__device__ void coop_drain(const SolveArgs &a, bool prefix_only, unsigned *queue, int *s_item)
+{
+    int item = uniform(*s_item);
+    __syncthreads();
+    while (item < a.n_items) {
+        const int c = uniform(a.order ? a.order[item] : item);
+        const int gid = uniform(a.grid_id ? a.grid_id[c] : 0);
+        const bool bad = (unsigned)gid >= (unsigned)a.n_grids;
+        if (prefix_only && (bad || uniform(a.grids[gid].n) != kCoopN))
+            break;
+        if (threadIdx.x == 0 && (!a.need || a.need[c])) {
+            a.status[c] = bad ? kStBadGrid : kStNotConverged;
+            if (a.phi)
+                a.phi[c] = __builtin_inf();
+        }
+        if (threadIdx.x == 0)
+            *s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        item = uniform(*s_item);
+        __syncthreads();
+    }
+}
+
+// Groups pull items from a queue of their own (the first word of the
+// workspace): member 0 takes the next index and the group exchange hands it
+// to the other members.  With `prefix_only` the queue is class-ordered and
+// the 256^2 items form its prefix: a group stops at the first item of
+// another class (or with an invalid class, which sorts last); a following
+// launch serves the rest.
+__device__ void coop_run(const SolveArgs &a, bool prefix_only, float *P, float *stash,
+                         double *red, double *gather, int *fail, int *s_item)
+{
+    // group of this workgroup: ids congruent modulo 8 share an XCD
+    const int b = blockIdx.x;
+    const int block32 = b / 32, lane32 = b % 32;
+    const int member = lane32 / 8;
+    const int group = block32 * 8 + lane32 % 8;
+    if (threadIdx.x == 0)
+        *fail = 0;
+    __syncthreads();
+    CoopCtx x;
+    x.base = (unsigned char *)a.coop + CoopArea::header_bytes + (size_t)group * CoopArea::group_bytes;
+    x.m = member;
+    x.seq = 0;
+    x.fail = fail;
+    x.gather = gather;
+    unsigned *queue = (unsigned *)a.coop;
+    float *slot = (float *)((char *)a.gws + (size_t)b * a.gws_stride);
+    for (;;) {
+        if (member == 0 && threadIdx.x == 0)
+            *s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        // members other than 0 contribute 0: the group sum is member 0's index
+        double v[1] = {member == 0 ? (double)*s_item : 0.0};
+        coop_exchange<1>(v, x);
+        if (*fail) {
+            // A member timed out (it cannot happen while every member is
+            // resident): the group stops exchanging, and member 0 marks
+            // the items it still pulls, its last one included, as failed.
+            if (member == 0)
+                coop_drain(a, prefix_only, queue, s_item);
+            break;
+        }
+        const int item = (int)(v[0] + 0.5);
+        if (item >= a.n_items)
+            break;
+        const int c = uniform(a.order ? a.order[item] : item);
+        const int gid = uniform(a.grid_id ? a.grid_id[c] : 0);
+        const bool bad = (unsigned)gid >= (unsigned)a.n_grids;
+        if (prefix_only && (bad || uniform(a.grids[gid].n) != kCoopN))
+            break;
+        if (a.need && !uniform(a.need[c]))
+            continue;
+        if (bad) {
+            if (threadIdx.x == 0 && member == 0) {
+                a.status[c] = kStBadGrid;
+                if (a.phi)
+                    a.phi[c] = __builtin_inf();
+            }
+            continue;
+        }
+        solve_item_coop(a, c, a.grids[gid], P, stash, red, slot, x);
+    }
+}
+
+__global__ __launch_bounds__(kCoopThreads) void k_solve_coop(SolveArgs a)
+{
+    constexpr int N = kCoopN, NS = kCoopStrip, NW = kCoopThreads / kWave;
+    __shared__ float P[(NS + 2) * N];
+    __shared__ float stash[NS * N];
+    __shared__ double red[Slots<NW>::total];
+    __shared__ double gather[kCoopG * 4];
+    __shared__ int fail;
+    __shared__ int s_item;
+    coop_run(a, a.coop_wgs > 0, P, stash, red, gather, &fail, &s_item);
+}
+
+
+template <int T, typename Real>
+__global__ __launch_bounds__(T) void k_solve_mixed(SolveArgs a)
+{
+    constexpr int NW = T / kWave;
+    constexpr int NM = MixedTraits<Real>::kMaxResident;
+    __shared__ Real P[NM * NM];
+    __shared__ Real stash[NM * NM];
+    __shared__ double red[Slots<NW>::total];
+    __shared__ int s_item;
+    Real *slot = (Real *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
+    for (int item = next_item(a.queue, &s_item); item < a.n_items;
+         item = next_item(a.queue, &s_item)) {
+        const int c = uniform(a.order ? a.order[item] : item);
+        const int gid = (!a.need || uniform(a.need[c])) ? item_grid(a, c) : -1;
+        if (gid >= 0) {
+            const GridDev &gd = a.grids[gid];
+            const int n = uniform(gd.n);
+            if (n == 32)
+                solve_item_class<32, T, Real>(a, c, gd, P, stash, red, slot);
+            else if (n == 64)
+                solve_item_class<64, T, Real>(a, c, gd, P, stash, red, slot);
+            else if (n == 128)
+                solve_item_class<128, T, Real>(a, c, gd, P, stash, red, slot);
+            else if (n == 256 && !a.coop_wgs)  // else the cooperative launch solved it
+                solve_item_class<256, T, Real>(a, c, gd, P, stash, red, slot);
+        }
+    }
+}
+
+
+// wgs: the most workgroups that are resident at once (every member of a
+// group must be, since members wait for each other).  The launch uses whole
+// blocks of 32 workgroups (8 groups, one per XCD) and no more groups than
+// items.  a.coop_wgs > 0 marks a class-ordered batch whose 256^2 prefix
+// this launch serves (the mixed launch that follows serves the rest).
+hipError_t launch_solve_coop(const SolveArgs &a, int wgs, hipStream_t s)
+{
+    const int need = (a.n_items * kCoopG + 31) / 32 * 32;
+    const int grid = std::min(wgs / 32 * 32, need);
+    if (!a.coop || !a.gws || grid < 32 || grid / kCoopG > a.coop_groups || grid > a.gws_slots ||
+        a.gws_stride < (size_t)4 * kCoopStrip * kCoopN * sizeof(float))
+        return hipErrorInvalidValue;
+    // the queue starts at 0, and stale tags of an earlier launch must not
+    // match this launch's
+    hipError_t e = launch_fill_u32((unsigned *)a.coop, 0u,
+                                   (int)(coop_workspace_bytes(grid / kCoopG) / sizeof(unsigned)), s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_solve_coop, dim3(grid), dim3(kCoopThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 // Per-class time-stepping coefficients of the growing domain rho = exp(r t):
 // dilution m rho'/rho = 2 r and the per-step factor of rho^-2, exp(-2 r dt).
 __global__ void k_grid_coeffs(GridDev *grids, int n_grids, double dt)
@@ -842,7 +1577,7 @@ hipError_t launch_fill_u32(unsigned *p, unsigned v, int count, hipStream_t s)
 // fit the VGPR budget of the workgroup size.
 namespace {
 
-enum Kind { kNone, kResident, kStreamed };
+enum Kind { kNone, kResident, kStreamed, kCoop };
 
 Kind tile_kind(int n, int precision, int cpt)
 {
@@ -853,6 +1588,8 @@ Kind tile_kind(int n, int precision, int cpt)
             return kResident;
         if (n == 128 && (cpt == 16 || cpt == 32))
             return kResident;
+        if (n == 256 && cpt == kCoopR)
+            return kCoop;
         if (n == 256 && (cpt == 64 || cpt == 128))
             return kStreamed;
     } else {
@@ -901,6 +1638,8 @@ int default_cpt(int n, int precision)
 
 size_t solve_slot_bytes(int n, int precision, int cpt)
 {
+    if (tile_kind(n, precision, cpt) == kCoop)  // one member's strip: 4 arrays
+        return (size_t)4 * kCoopStrip * kCoopN * sizeof(float);
     const size_t arrays = tile_kind(n, precision, cpt) == kStreamed ? 10 : 4;
     return arrays * n * n * (precision ? sizeof(double) : sizeof(float));
 }
@@ -922,6 +1661,8 @@ int solve_wgs_per_cu(int n, int precision, int cpt)
 #define RD_OCC_S(NN, RR, T)                                                     \
     if (n == NN && cpt == RR)                                                   \
         return occupancy(k_solve_streamed<NN, RR, T>, NN * NN / RR);
+    if (tile_kind(n, precision, cpt) == kCoop)
+        return occupancy(k_solve_coop, kCoopThreads);
     if (precision == 0) {
         RD_OCC_R(32, 4, float) RD_OCC_R(32, 8, float) RD_OCC_R(32, 16, float)
         RD_OCC_R(64, 4, float) RD_OCC_R(64, 8, float) RD_OCC_R(64, 16, float)
@@ -997,6 +1738,11 @@ bool tile_streamed(int n, int precision, int cpt)
     return tile_kind(n, precision, cpt) == kStreamed;
 }
 
+bool tile_coop(int n, int precision, int cpt)
+{
+    return tile_kind(n, precision, cpt) == kCoop;
+}
+
 hipError_t launch_solve(int n, int precision, TileChoice tile, const SolveArgs &a, int wgs,
                         hipStream_t s)
 {
@@ -1011,6 +1757,8 @@ hipError_t launch_solve(int n, int precision, TileChoice tile, const SolveArgs &
 #define RD_STR(NN, RR, T)                                     \
     if (n == NN && cpt == RR)                                 \
         return go_streamed<NN, RR, T>(a, wgs, s);
+    if (tile_kind(n, precision, cpt) == kCoop)
+        return launch_solve_coop(a, wgs, s);
     if (precision == 0) {
         RD_RES(32, 4, float) RD_RES(32, 8, float) RD_RES(32, 16, float)
         RD_RES(64, 4, float) RD_RES(64, 8, float) RD_RES(64, 16, float)

@@ -1,0 +1,104 @@
+"""Cooperative 256 x 256 FP32 tile (four workgroups per item, 64-row strips,
+edge rows and CG sums exchanged through global memory) vs the FP64 oracle,
+through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import THETA_TRUE, TAU, make_problem, need_gpu, rel_l2, theta_batch
+from paper_1605_04718_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+COOP_CPT = 16       # cells per thread of the cooperative tile at 256^2
+STREAMED_CPT = 128  # the single-workgroup streamed tile
+
+
+def run(p, thetas):
+    import torch
+    th = torch.tensor(np.asarray(thetas), dtype=torch.float64, device="cuda")
+    u, v, st, it = p.forward_solve(th)
+    torch.cuda.synchronize()
+    return u.double().cpu().numpy(), v.double().cpu().numpy(), st.cpu().numpy(), it.cpu().numpy()
+
+
+def test_coop_256_fields_and_misfit_match_oracle():
+    """Several CG iterations per solve, the predictor from the second step
+    on, and the group-summed misfit."""
+    import torch
+    need_gpu()
+    steps = 6
+    n = 256
+    u0, v0 = inputs.initial_fields(n, THETA_TRUE[0], THETA_TRUE[1])
+    uo_true, _, _, _ = oracle.forward_solve(THETA_TRUE, u0, v0, TAU, steps, rtol=1e-12)
+    y, sigma = inputs.noisy_data(uo_true, 0.01)
+    thetas = np.vstack([THETA_TRUE, theta_batch(2, seed=41)])
+    p, _, _ = make_problem(n, steps, precision=0, maxit=4000, y=y, sigma=sigma, u0=u0, v0=v0)
+    p.set_tile(0, COOP_CPT)
+    print(f"coop 256: {len(thetas)} items, {steps} steps", flush=True)
+    ug, vg, st, it = run(p, thetas)
+    phi, st2, _ = p.log_likelihood(torch.tensor(thetas, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    phi = phi.cpu().numpy()
+    want, sto, _ = oracle.loglik_batch(thetas, u0, v0, y, sigma, TAU, steps, rtol=1e-12)
+    for k, th in enumerate(thetas):
+        uo, vo, ito, so = oracle.forward_solve(th, u0, v0, TAU, steps, rtol=1e-12)
+        assert st[k] == 0 and so == 0 and int(st2[k]) == 0
+        assert rel_l2(ug[k], uo) < 1e-5 and rel_l2(vg[k], vo) < 1e-5, (k, rel_l2(ug[k], uo),
+                                                                        rel_l2(vg[k], vo))
+        assert np.all(it[k] > 0)
+        # misfit: sum of n^2 squared residuals of size ~sigma; the field
+        # error (<= 1e-5 relative) moves it by far less than 1e-3 relative
+        assert abs(phi[k] - want[k]) <= 1e-3 * abs(want[k]) + 1e-6, (phi[k], want[k])
+    p.close()
+
+
+def test_coop_256_growing_domain_matches_oracle():
+    need_gpu()
+    steps, rate = 5, 0.4
+    thetas = np.vstack([THETA_TRUE, theta_batch(1, seed=43)])
+    p, u0, v0 = make_problem(256, steps, precision=0, maxit=4000, growth=1, rate=rate)
+    p.set_tile(0, COOP_CPT)
+    print(f"coop 256 growing: {len(thetas)} items, {steps} steps", flush=True)
+    ug, vg, st, it = run(p, thetas)
+    for k, th in enumerate(thetas):
+        uo, vo, ito, so = oracle.forward_solve(th, u0, v0, TAU, steps, growth=1, rate=rate,
+                                               rtol=1e-12)
+        assert st[k] == 0 and so == 0
+        assert rel_l2(ug[k], uo) < 1e-5 and rel_l2(vg[k], vo) < 1e-5, (k, rel_l2(ug[k], uo))
+    p.close()
+
+
+def test_coop_256_more_items_than_groups():
+    """Each group takes several items in turn; sampled items against the
+    oracle, every item against the streamed single-workgroup tile."""
+    need_gpu()
+    steps, m = 2, 150
+    thetas = theta_batch(m, seed=47)
+    p, u0, v0 = make_problem(256, steps, precision=0, maxit=4000, max_batch=m)
+    p.set_tile(0, COOP_CPT)
+    print(f"coop 256: {m} items, {steps} steps", flush=True)
+    ug, vg, st, _ = run(p, thetas)
+    assert np.all(st == 0)
+    for k in (0, 1, 70, m - 1):
+        uo, vo, _, so = oracle.forward_solve(thetas[k], u0, v0, TAU, steps, rtol=1e-12)
+        assert so == 0
+        assert rel_l2(ug[k], uo) < 1e-5 and rel_l2(vg[k], vo) < 1e-5, (k, rel_l2(ug[k], uo))
+    p.set_tile(0, STREAMED_CPT)
+    print(f"streamed 256: {m} items, {steps} steps", flush=True)
+    us, vs, ss, _ = run(p, thetas)
+    assert np.all(ss == 0)
+    for k in range(m):
+        assert rel_l2(ug[k], us[k]) < 2e-5 and rel_l2(vg[k], vs[k]) < 2e-5, k
+    p.close()
+
+
+def test_set_tile_rejects_unsupported():
+    from paper_1605_04718_amd._lib import RDError
+    need_gpu()
+    p, _, _ = make_problem(256, 1, precision=1)
+    with pytest.raises(RDError):
+        p.set_tile(0, COOP_CPT)  # the cooperative tile is FP32 only
+    with pytest.raises(RDError):
+        p.set_tile(1, STREAMED_CPT)
+    p.close()
