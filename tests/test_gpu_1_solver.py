@@ -72,6 +72,7 @@ def test_fp32_streamed_256_matches_oracle():
     need_gpu()
     thetas = np.vstack([THETA_TRUE])
     p, u0, v0 = make_problem(256, 3, precision=0, maxit=3000)
+    p.set_tile(0, 128)  # the single-workgroup streamed tile (the default is cooperative)
     ug, vg, st, it = run_gpu(p, thetas)
     uo, vo, ito, sto = oracle_fields(thetas, u0, v0, 3)[0]
     assert st[0] == 0
