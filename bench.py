@@ -45,6 +45,10 @@ LO = (0.0, 0.0, math.log(50.0), math.log(5.0))
 HI = (1.0, 1.0, math.log(500.0), math.log(50.0))
 CG_RTOL = 1e-7
 CG_MAXIT = 400
+# The uneven workload's largest class (256^2) needs up to ~350 CG iterations
+# per step in its first steps (d = 50); CG iteration counts grow about
+# linearly with n, so its cap is four times the 128^2 one.
+CG_MAXIT_MIXED = 1600
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed); FLOP/s
 # Algorithmic FP operations of the fused solve (per cell, per species; a
 # fused multiply-add counts 2):
@@ -257,9 +261,10 @@ def stationary_leg(args, u0, v0, y, sigma, log):
 def mixed_leg(args, log):
     """The uneven workload: chains split 4:2:1 over 64^2, 128^2 and 256^2
     grids, half on stationary and half on growing domains (rho = e^{0.01 t}),
-    six datasets; per step a cooperative launch for the 256^2 items and a
-    persistent launch for the other classes, the step replayed from a
-    captured graph; wall-clock cell-steps/s of the solves performed."""
+    six datasets; per step one launch (1024-thread workgroups: groups of four
+    solve the 256^2 items, then join the other classes) or two (512: a
+    cooperative launch, then the mixed one), replayed from a captured graph;
+    wall-clock cell-steps/s of the solves performed."""
     import torch
     from paper_1605_04718_amd import inputs
     from paper_1605_04718_amd.api import ChainState, Grid, Problem
@@ -273,7 +278,7 @@ def mixed_leg(args, log):
         grids.append((n, growth, u0, v0))
     # data: each class's own noise-free field at theta_true from the library
     gen = Problem([Grid(n=n, u0=u0, v0=v0, growth=g, growth_rate=0.01 if g else 0.0)
-                   for n, g, u0, v0 in grids], TAU, n_steps, CG_RTOL, cg_maxit=CG_MAXIT,
+                   for n, g, u0, v0 in grids], TAU, n_steps, CG_RTOL, cg_maxit=CG_MAXIT_MIXED,
                   max_batch=len(classes))
     th = torch.tensor([THETA_TRUE] * len(classes), dtype=torch.float64, device="cuda")
     gid = torch.arange(len(classes), dtype=torch.int32, device="cuda")
@@ -294,15 +299,20 @@ def mixed_leg(args, log):
     C = len(ids)
     ids = torch.tensor(np.array(ids, dtype=np.int32), device="cuda")
     step = tuple(0.02 * (h - l) for l, h in zip(LO, HI))
-    p = Problem(gl, TAU, n_steps, CG_RTOL, cg_maxit=CG_MAXIT, lo=LO, hi=HI, step=step,
+    p = Problem(gl, TAU, n_steps, CG_RTOL, cg_maxit=CG_MAXIT_MIXED, lo=LO, hi=HI, step=step,
                 max_batch=C)
     p.autotune()
     T = p.mixed_threads()
     log(f"mixed: autotuned workgroup {T} threads; initial misfits of {C} chains")
     phi0 = inputs.box_draws(C, LO, HI, seed=inputs.SEED_CHAIN_INIT)
-    ll0, _, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"), grid_id=ids)
+    ll0, st0, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"),
+                                   grid_id=ids)
     torch.cuda.synchronize()
-    log("mixed: initial misfits done")
+    st0 = st0.cpu().numpy()
+    idn0 = ids.cpu().numpy()
+    failed0 = {f"{n}{'g' if g else 's'}": int((st0[idn0 == k] != 0).sum())
+               for k, (n, g, _, _) in enumerate(grids)}
+    log(f"mixed: initial misfits done; failed solves per class {failed0}")
     ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0, seed=inputs.SEED_SAMPLER,
                            grid_id=ids)
     stream = torch.cuda.Stream()
@@ -334,10 +344,14 @@ def mixed_leg(args, log):
     return {"workload": f"{C} chains: {counts[64]} x 64^2, {counts[128]} x 128^2, "
                         f"{counts[256]} x 256^2 (the 4:2:1 mix at {args.mixed_scale:g} of 4095 "
                         "chains), half stationary and half growing (rho = exp(0.01 t)), 6 datasets, "
-                        "T=2, per step a cooperative launch for the 256^2 items and a "
-                        "persistent launch for the rest, replayed from a captured graph",
+                        "T=2, " + ("one launch per step (256^2 items by groups of four "
+                                   "workgroups, then the other classes)" if T == 1024 else
+                                   "per step a cooperative launch for the 256^2 items and a "
+                                   "persistent launch for the rest") +
+                        ", replayed from a captured graph",
             "cell_steps_per_s": cell_steps / wall, "ms_per_step": 1e3 * wall / args.steps,
-            "mixed_threads": T, "solves_per_class": per}
+            "mixed_threads": T, "solves_per_class": per, "cg_maxit": CG_MAXIT_MIXED,
+            "initial_failed_solves_per_class": failed0}
 
 
 def main():

@@ -284,6 +284,14 @@ int32_t rd_autotune(rd_problem *p, int32_t *cpt_out);
  * kernel for that cpt at this size and precision). */
 int32_t rd_set_tile(rd_problem *p, int32_t grid, int32_t cpt);
 
+/* Sets the workgroup size (512 or 1024) of the launch that serves batches
+ * mixing grid classes, overriding the default and any cached choice for
+ * this problem only.  With 1024 and 256 x 256 FP32 classes, one launch
+ * serves all classes (the 256 x 256 items by groups of four workgroups);
+ * with 512 a cooperative launch for those items precedes the mixed launch.
+ * Errors: RD_EINVAL (NULL problem, other sizes). */
+int32_t rd_set_mixed_threads(rd_problem *p, int32_t threads);
+
 /* Workgroup size of the launch that serves batches mixing grid classes
  * (host int32 out).  Errors: RD_EINVAL (NULL argument). */
 int32_t rd_mixed_threads(const rd_problem *p, int32_t *threads);

@@ -61,6 +61,7 @@ SYMBOLS = {
     "surrogate_params": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_vp]),
     "rd_autotune": (c_i32, [c_vp, c_vp]),
     "rd_set_tile": (c_i32, [c_vp, c_i32, c_i32]),
+    "rd_set_mixed_threads": (c_i32, [c_vp, c_i32]),
     "rd_solver_timing": (c_i32, [c_vp, c_i32, c_dp, ctypes.POINTER(c_i64), c_i32]),
     "rd_mixed_threads": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),
     "surrogate_set_input_box": (c_i32, [c_vp, c_dp, c_dp]),

@@ -249,6 +249,10 @@ class Problem:
         """Select grid class `grid`'s tile by cells per thread."""
         check(lib().rd_set_tile(self.h, int(grid), int(cpt)), "rd_set_tile")
 
+    def set_mixed_threads(self, threads):
+        """Workgroup size (512 or 1024) of the launch for batches mixing classes."""
+        check(lib().rd_set_mixed_threads(self.h, int(threads)), "rd_set_mixed_threads")
+
     def mixed_threads(self):
         """Workgroup size of the launch that serves batches mixing grid classes."""
         t = ctypes.c_int32()

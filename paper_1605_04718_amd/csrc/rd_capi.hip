@@ -96,6 +96,7 @@ struct rd_problem {
     void *coop = nullptr;    // cooperative-solve workspace (256^2 FP32)
     int coop_groups = 0;
     int coop_wpc = 0;        // resident cooperative workgroups per CU
+    int mixed_coop_wpc = 0;  // resident workgroups per CU of the fused mixed launch
     // timing of the fused solve kernel
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -187,18 +188,21 @@ hipError_t record_solve_end(rd_problem *p, hipStream_t s, hipEvent_t start)
 }
 
 // Enqueue: reset the queue head, then the persistent fused solve.
+// Without grid ids every item is of class `cls` (0 for the public calls;
+// the autotuner times each class on its own).
 int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid_id,
                       const int *need, double *phi, int *status, int *iters, void *u_out,
-                      void *v_out, hipStream_t s)
+                      void *v_out, hipStream_t s, int cls = 0)
 {
     if (n == 0)
         return RD_OK;
     const bool mixed = p->desc.n_grids > 1 && grid_id;
-    const int g = 0;
+    const int g = mixed ? 0 : cls;
     const int nn = p->grids_host[g].n;
     SolveArgs a{};
-    a.grids = p->grids_dev;
-    a.n_grids = p->desc.n_grids;
+    // single-class launches see class g as their only class
+    a.grids = mixed ? p->grids_dev : p->grids_dev + g;
+    a.n_grids = mixed ? p->desc.n_grids : 1;
     a.n_items = n;
     a.order = nullptr;
     a.grid_id = grid_id;
@@ -227,13 +231,22 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     // (a cooperative tile sizes its grid from the item count itself)
     if (wgs > n && (mixed || !tile_coop(nn, p->desc.precision, t.cpt)))
         wgs = n;
-    // batches mixing classes: a cooperative launch first serves the 256^2
-    // FP32 items (the prefix of the class-ordered queue) in groups of four
-    // workgroups, then the mixed launch serves the other classes
+    // batches mixing classes with 256^2 FP32 items: groups of four resident
+    // workgroups serve them (the prefix of the class-ordered queue).  With
+    // 1024-thread workgroups one launch does both (the cooperative
+    // workgroups join the other classes' queue when the prefix is done);
+    // with 512 a cooperative launch runs first and the mixed launch skips
+    // the 256^2 items.
     a.coop_wgs = 0;
     int coop_grid = 0;
+    const bool fused = p->mixed_threads == kCoopThreads;
     if (mixed && p->coop && p->desc.precision == 0) {
-        coop_grid = std::min(p->n_cu * p->coop_wpc / 32 * 32, p->coop_groups * kCoopG);
+        // every workgroup of the fused launch is resident at once, and the
+        // cooperative role takes whole blocks of 32 (small batches too)
+        if (fused)
+            wgs = std::min(std::max(wgs, 32), p->n_cu * p->mixed_coop_wpc);
+        coop_grid = std::min((fused ? wgs : p->n_cu * p->coop_wpc) / 32 * 32,
+                             p->coop_groups * kCoopG);
         a.coop_wgs = coop_grid >= 32 ? coop_grid : 0;
     }
     HIP_TRY(launch_fill_u32(p->queue, 0u, 1, s));
@@ -243,12 +256,15 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     }
     hipEvent_t e0;
     HIP_TRY(record_solve_start(p, s, &e0));
-    if (mixed && a.coop_wgs)
-        HIP_TRY(launch_solve_coop(a, coop_grid, s));
-    if (mixed)
-        HIP_TRY(launch_solve_mixed(p->desc.precision, p->mixed_threads, a, wgs, s));
-    else
+    if (!mixed) {
         HIP_TRY(launch_solve(nn, p->desc.precision, t, a, wgs, s));
+    } else if (a.coop_wgs && fused) {
+        HIP_TRY(launch_solve_mixed_coop(a, wgs, s));
+    } else {
+        if (a.coop_wgs)
+            HIP_TRY(launch_solve_coop(a, coop_grid, s));
+        HIP_TRY(launch_solve_mixed(p->desc.precision, p->mixed_threads, a, wgs, s));
+    }
     HIP_TRY(record_solve_end(p, s, e0));
     return RD_OK;
 }
@@ -508,6 +524,7 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         for (int cpt : {4, 8, 16, 32, 64, 128}) {
             if (tile_coop(n, desc->precision, cpt) && !p->coop) {
                 p->coop_wpc = solve_wgs_per_cu(n, desc->precision, cpt);
+                p->mixed_coop_wpc = mixed_coop_wgs_per_cu();
                 p->coop_groups = p->n_cu * p->coop_wpc / kCoopG + 8;
                 p->coop = dmalloc(p, coop_workspace_bytes(p->coop_groups), &err);
             }
@@ -746,10 +763,12 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
     if (!p)
         return fail(RD_EINVAL, "problem is NULL");
     // Trial: one solve per resident workgroup slot over a short horizon, on
-    // the homogeneous-state parameters of the prior centre.
-    const int trial_steps = std::min(p->desc.n_steps, 160);
+    // a low-discrepancy spread of the prior box; grids above 128^2 run
+    // fewer steps (their tiles cost up to seconds per 160 steps).
     for (int g = 0; g < p->desc.n_grids; ++g) {
         const int n = p->grids_host[g].n;
+        const int trial_steps =
+            std::min(p->desc.n_steps, n > 128 ? std::max(20, 160 * 128 * 128 / (n * n)) : 160);
         int best = p->tile[g].cpt;
         float best_ms = 1e30f;
         for (int cpt : {4, 8, 16, 32, 64, 128}) {
@@ -781,11 +800,11 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
             const bool saved_timing = p->timing;
             p->timing = false;
             int32_t r = enqueue_solve(p, items, d_th, nullptr, nullptr, nullptr, d_st, nullptr,
-                                      nullptr, nullptr, nullptr);
+                                      nullptr, nullptr, nullptr, g);
             hipEventRecord(e0, nullptr);
             if (r == RD_OK)
                 r = enqueue_solve(p, items, d_th, nullptr, nullptr, nullptr, d_st, nullptr,
-                                  nullptr, nullptr, nullptr);
+                                  nullptr, nullptr, nullptr, g);
             hipEventRecord(e1, nullptr);
             hipEventSynchronize(e1);
             float ms = 0.f;
@@ -825,6 +844,7 @@ extern "C" int32_t rd_autotune(rd_problem *p, int32_t *cpt_out)
     if (p->desc.n_grids > 1) {
         // Mixed launch: workgroup size, on a batch that cycles through the
         // classes (one item per workgroup slot).
+        const int trial_steps = std::min(p->desc.n_steps, 160);
         int best = p->mixed_threads;
         float best_ms = 1e30f;
         for (int threads : {512, 1024}) {
@@ -908,6 +928,17 @@ extern "C" int32_t rd_set_tile(rd_problem *p, int32_t grid, int32_t cpt)
     // the workspace was sized for every supported tile of this class
     p->tile[grid] = TileChoice{cpt, n * n / cpt};
     p->wgs_per_cu[grid] = solve_wgs_per_cu(n, p->desc.precision, cpt);
+    return RD_OK;
+}
+
+extern "C" int32_t rd_set_mixed_threads(rd_problem *p, int32_t threads)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    if (threads != 512 && threads != 1024)
+        return fail(RD_EINVAL, "threads must be 512 or 1024, got %d", threads);
+    p->mixed_threads = threads;
+    p->mixed_wpc = mixed_wgs_per_cu(p->desc.precision, threads);
     return RD_OK;
 }
 

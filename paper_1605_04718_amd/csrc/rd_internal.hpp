@@ -67,6 +67,8 @@ constexpr int kCoopG = 4;         // workgroups per item (horizontal strips of 6
 constexpr int kCoopThreads = 1024;
 __host__ __device__ size_t coop_workspace_bytes(int groups);
 hipError_t launch_solve_coop(const SolveArgs &a, int grid_wgs, hipStream_t s);
+hipError_t launch_solve_mixed_coop(const SolveArgs &a, int grid_wgs, hipStream_t s);
+int mixed_coop_wgs_per_cu();
 
 // Class ranks of a mixed batch (queue order: rank 0 first).
 constexpr int kMaxClasses = 8;

@@ -1517,6 +1517,43 @@ __global__ __launch_bounds__(T) void k_solve_mixed(SolveArgs a)
 }
 
 
+// Mixed launch with the cooperative role (FP32, 1024 threads): the first
+// a.coop_wgs workgroups (a multiple of 32, all resident: they have the
+// lowest ids, so they are dispatched first) serve the 256^2 prefix of the
+// class-ordered queue in groups of four, then join the queue of the other
+// classes, which the remaining workgroups serve from the start.  Classes
+// 32^2 .. 128^2 run resident.
+__global__ __launch_bounds__(kCoopThreads) void k_solve_mixed_coop(SolveArgs a)
+{
+    constexpr int T = kCoopThreads, NW = T / kWave, NM = 128;
+    constexpr int kP = (kCoopStrip + 2) * kCoopN;
+    static_assert(kP >= NM * NM, "LDS P holds a 128^2 item");
+    __shared__ float P[kP];
+    __shared__ float stash[NM * NM];
+    __shared__ double red[Slots<NW>::total];
+    __shared__ double gather[kCoopG * 4];
+    __shared__ int fail;
+    __shared__ int s_item;
+    if ((int)blockIdx.x < a.coop_wgs)
+        coop_run(a, true, P, stash, red, gather, &fail, &s_item);
+    float *slot = (float *)((char *)a.gws + (size_t)blockIdx.x * a.gws_stride);
+    for (int item = next_item(a.queue, &s_item); item < a.n_items;
+         item = next_item(a.queue, &s_item)) {
+        const int c = uniform(a.order ? a.order[item] : item);
+        const int gid = (!a.need || uniform(a.need[c])) ? item_grid(a, c) : -1;
+        if (gid >= 0) {
+            const GridDev &gd = a.grids[gid];
+            const int n = uniform(gd.n);
+            if (n == 32)
+                solve_item_class<32, T, float>(a, c, gd, P, stash, red, slot);
+            else if (n == 64)
+                solve_item_class<64, T, float>(a, c, gd, P, stash, red, slot);
+            else if (n == 128)
+                solve_item_class<128, T, float>(a, c, gd, P, stash, red, slot);
+        }
+    }
+}
+
 // wgs: the most workgroups that are resident at once (every member of a
 // group must be, since members wait for each other).  The launch uses whole
 // blocks of 32 workgroups (8 groups, one per XCD) and no more groups than
@@ -1732,6 +1769,29 @@ hipError_t launch_solve_mixed(int precision, int threads, const SolveArgs &a, in
         else
             hipLaunchKernelGGL((k_solve_mixed<1024, double>), dim3(wgs), dim3(1024), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+int mixed_coop_wgs_per_cu()
+{
+    return occupancy(k_solve_mixed_coop, kCoopThreads);
+}
+
+// Mixed batch with 256^2 FP32 items and 1024-thread workgroups: one launch
+// of k_solve_mixed_coop (a.coop_wgs leading workgroups in the cooperative
+// role).  The caller has class-ordered the queue (a.order).
+hipError_t launch_solve_mixed_coop(const SolveArgs &a, int wgs, hipStream_t s)
+{
+    if (!a.gws || !a.order || !a.coop || wgs > a.gws_slots || a.coop_wgs < 32 ||
+        a.coop_wgs % 32 != 0 || a.coop_wgs > wgs || a.coop_wgs / kCoopG > a.coop_groups ||
+        a.gws_stride < (size_t)4 * kCoopStrip * kCoopN * sizeof(float))
+        return hipErrorInvalidValue;
+    hipError_t e = launch_fill_u32((unsigned *)a.coop, 0u,
+                                   (int)(coop_workspace_bytes(a.coop_wgs / kCoopG) / sizeof(unsigned)),
+                                   s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_solve_mixed_coop, dim3(wgs), dim3(kCoopThreads), 0, s, a);
     return hipGetLastError();
 }
 

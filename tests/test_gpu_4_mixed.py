@@ -45,11 +45,16 @@ def batch_ids(m, seed=5):
     return ids.astype(np.int32)
 
 
-def test_mixed_batch_matches_oracle_per_class():
+@pytest.mark.parametrize("threads", [1024, 512])
+def test_mixed_batch_matches_oracle_per_class(threads):
+    """1024 threads: one launch, 256^2 items by the cooperative role first;
+    512: a cooperative launch, then the mixed launch for the other classes."""
     import torch
     need_gpu()
     steps = 5
     p, fields = classes_problem(steps)
+    p.set_mixed_threads(threads)
+    assert p.mixed_threads() == threads
     ids = batch_ids(14)
     thetas = np.vstack([THETA_TRUE, theta_batch(len(ids) - 1, seed=31)])
     th = torch.tensor(thetas, device="cuda")
