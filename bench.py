@@ -18,10 +18,14 @@ on a bounded number of the library's own prior solves first, then runs the
 same number of steps from the same chain states: every proposal is screened
 by the surrogate and only stage-1 passes are solved.
 
+The uneven leg (the `mixed` block, skipped with --no-mixed) runs 4095
+chains split 4:2:1 over 64^2, 128^2 and 256^2 grids, half on growing
+domains, in one launch per step.
+
 Prints one JSON line: value = PDE cell-steps per second of the plain
 sampler (solves actually performed), the roofline of the fused solve
-kernel, the FP64 CPU oracle baseline, and the delayed-acceptance figures
-beside the plain ones.
+kernel, the FP64 CPU oracle baseline, the delayed-acceptance figures
+beside the plain ones, and the uneven leg.
 """
 from __future__ import annotations
 
@@ -326,7 +330,7 @@ def mixed_leg(args, log):
         log(f"mixed warmup (2 steps, the second captured): {time.time() - t:.1f} s")
         per_class0 = ch.n_solves.cpu().numpy().copy()
         t0 = time.time()
-        for k in range(args.steps):
+        for k in range(args.mixed_steps):
             p.mcmc_step(ch, 1)
             stream.synchronize()
             log(f"mixed timed step {k}: {time.time() - t0:.1f} s elapsed")
@@ -340,7 +344,7 @@ def mixed_leg(args, log):
         per[f"{n}{'g' if g else 's'}"] = sk
         cell_steps += sk * n * n * n_steps
     p.close()
-    log(f"mixed: {C} chains, workgroup {T} threads, {args.steps} steps in {wall:.2f} s")
+    log(f"mixed: {C} chains, workgroup {T} threads, {args.mixed_steps} steps in {wall:.2f} s")
     return {"workload": f"{C} chains: {counts[64]} x 64^2, {counts[128]} x 128^2, "
                         f"{counts[256]} x 256^2 (the 4:2:1 mix at {args.mixed_scale:g} of 4095 "
                         "chains), half stationary and half growing (rho = exp(0.01 t)), 6 datasets, "
@@ -349,7 +353,8 @@ def mixed_leg(args, log):
                                    "per step a cooperative launch for the 256^2 items and a "
                                    "persistent launch for the rest") +
                         ", replayed from a captured graph",
-            "cell_steps_per_s": cell_steps / wall, "ms_per_step": 1e3 * wall / args.steps,
+            "cell_steps_per_s": cell_steps / wall, "ms_per_step": 1e3 * wall / args.mixed_steps,
+            "steps": args.mixed_steps,
             "mixed_threads": T, "solves_per_class": per, "cg_maxit": CG_MAXIT_MIXED,
             "initial_failed_solves_per_class": failed0}
 
@@ -366,8 +371,12 @@ def main():
     ap.add_argument("--sur-solves", type=int, default=16384,
                     help="prior solves the surrogate is trained on in the DA leg")
     ap.add_argument("--sur-epochs", type=int, default=40)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the uneven 64/128/256 workload (the `mixed` block)")
     ap.add_argument("--mixed", action="store_true",
-                    help="also run the uneven 64/128/256 workload in one persistent launch")
+                    help="(default) run the uneven workload; kept for older command lines")
+    ap.add_argument("--mixed-steps", type=int, default=1,
+                    help="timed steps of the uneven workload")
     ap.add_argument("--mixed-scale", type=float, default=1.0,
                     help="fraction of the 4095 chains of the uneven workload")
     ap.add_argument("--stationary", action="store_true",
@@ -520,7 +529,7 @@ def main():
         }
         line["ess"]["da"] = ess_block(da_trace, dwall)
 
-    if args.mixed:
+    if not args.no_mixed:
         line["mixed"] = mixed_leg(args, log)
     if args.stationary:
         line["stationary"] = stationary_leg(args, u0, v0, y, sigma, log)
