@@ -952,10 +952,63 @@ __device__ __forceinline__ void coop_sync(CoopCtx &x)
 
 // Sums of M per-thread values over the group's threads.
 template <int NW, int M>
-__device__ __forceinline__ void coop_sum(double (&v)[M], double *red, CoopCtx &x)
+__device__ void coop_sum(double (&v)[M], double *red, CoopCtx &x)
 {
-    block_sum_n<NW>(v, red);
-    coop_exchange<M>(v, x);
+    // as block_sum_n followed by coop_exchange, with one workgroup barrier
+    // fewer: the lanes that publish form this member's sums themselves
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        v[m] = wave_sum_last_lane(v[m]);
+    // this thread's coherent stores are complete before the value is published
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    const int t = threadIdx.x;
+    if ((t & (kWave - 1)) == kLastLane) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            red[m * NW + t / kWave] = v[m];
+    }
+    __syncthreads();
+    x.seq += 1;
+    const unsigned tag = x.seq & 0xFFu;
+    double *buf = x.partial(x.seq);
+    if (t < kCoopG * M) {
+        const int mm = t / M, j = t % M;  // lane t: value j of member mm
+        double got = 0.0;
+        if (mm == x.m) {
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                sum += red[j * NW + w];
+            got = with_tag(sum, tag);
+            coop_store(buf + lane_off(x.m * 4 + j), got);
+        }
+        asm volatile("" ::: "memory");  // the store is issued before any poll
+        if (mm != x.m && !*x.fail) {
+            got = coop_load(buf + lane_off(mm * 4 + j));
+            if (tag_of(got) != tag) {
+                const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+                do {
+                    __builtin_amdgcn_s_sleep(1);
+                    got = coop_load(buf + lane_off(mm * 4 + j));
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > kCoopWaitTicks) {
+                        *x.fail = 1;
+                        break;
+                    }
+                } while (tag_of(got) != tag);
+            }
+        }
+        x.gather[t] = got;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double sum = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < kCoopG; ++mm)
+            sum += x.gather[mm * M + j];
+        v[j] = uniform(sum);
+    }
 }
 
 // Thread layout of a member: thread t owns column i = t % N, local rows
