@@ -117,6 +117,33 @@ __device__ __forceinline__ void sweep(const Real *P, const Geo<N, R> &g, F &&f)
     }
 }
 
+// sweep() over two arrays with the same layout at once: f(k, p_c, t(p),
+// q_c, t(q)).
+template <int N, int R, int U, typename Real, typename F>
+__device__ __forceinline__ void sweep_pair(const Real *P, const Real *Q, const Geo<N, R> &g, F &&f)
+{
+    Real cur = P[g.j0 * N + g.i], qcur = Q[g.j0 * N + g.i];
+    Real south = (g.j0 > 0) ? P[(g.j0 - 1) * N + g.i] : cur;
+    Real qsouth = (g.j0 > 0) ? Q[(g.j0 - 1) * N + g.i] : qcur;
+#pragma unroll U
+    for (int k = 0; k < R; ++k) {
+        const int j = g.j0 + k;
+        const bool in = k + 1 < R || j + 1 < N;
+        const Real north = in ? P[(j + 1) * N + g.i] : cur;
+        const Real qnorth = in ? Q[(j + 1) * N + g.i] : qcur;
+        const Real t = ((cur - P[j * N + g.iw]) + (cur - P[j * N + g.ie])) +
+                       ((cur - south) + (cur - north));
+        const Real qt = ((qcur - Q[j * N + g.iw]) + (qcur - Q[j * N + g.ie])) +
+                        ((qcur - qsouth) + (qcur - qnorth));
+        f(k, cur, t, qcur, qt);
+        south = cur;
+        cur = north;
+        qsouth = qcur;
+        qcur = qnorth;
+        RD_GROUP_FENCE(k)
+    }
+}
+
 // P <- own cells of a global array (src = own-cell pointer, cell k at
 // src[k N]).  kLds: P is in LDS (resident variant).  When the 64 lanes of a wave own 64 consecutive words of every
 // strip row (N >= 64) the copy uses direct global->LDS loads, which need no
@@ -181,13 +208,20 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 // trajectory is smooth in time this removes the part of r0 that the last
 // step predicts.  The system and the stopping test are unchanged:
 // |r| <= rtol |b| on the recursively updated residual.
-template <int N, int R, int U, int NW, bool kLds, int kSp, typename Real, class Arr, class SArr>
+//
+// kFuse (resident FP32): on entry the other species' field is still in
+// registers (Sreg) and the LDS stash behind S is free.  The residuals of hi
+// and of lo are then formed in one pass, lo staged in the stash, and Sreg
+// is parked in the stash afterwards (S reads it from there on).
+template <int N, int R, int U, int NW, bool kLds, int kSp, bool kFuse = false, typename Real,
+          class Arr, class SArr>
 __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Real inv_dt, Real c,
                         Real src, Real dl, Real gam, double rtol2, int maxit, Real *P,
                         const Real *lo, const Real *H, bool pred, double *red, const Geo<N, R> &g,
-                        int &it_acc)
+                        int &it_acc, const Arr *Sreg = nullptr, Real *stash = nullptr)
 {
     constexpr bool comp = Compensated<Real>::on;
+    static_assert(!kFuse || (comp && kLds), "the fused set-up is for resident FP32 solves");
     // e(k) and sigma(k) = 1/dt + e(k)
     const Real e0 = uniform(kSp == 0 ? dl + gam : dl);
     const Real s0 = uniform(e0 + inv_dt);
@@ -203,6 +237,43 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         else
             return s0 + gam * (S[k] * S[k]);
     };
+    double bb = 0.0, rr = 0.0;
+    if constexpr (kFuse) {
+        const Arr &Sr = *Sreg;
+        auto e_reg = [&](int k) -> Real {
+            if constexpr (kSp == 0)
+                return e0 - gam * (hi[k] * Sr[k]);
+            else
+                return e0 + gam * (Sr[k] * Sr[k]);
+        };
+        // the stash's last reads (own cells) are complete before lo lands there
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        copy_to_lds<N, R, U, kLds>(lo + g.off(), stash, g);
+#pragma unroll U
+        for (int k = 0; k < R; ++k) {
+            P[g.idx(k)] = hi[k];
+            RD_GROUP_FENCE(k)
+        }
+        __syncthreads();
+        // r0 = src - e x - c t(x) for x = hi + lo, the same arithmetic as the
+        // two passes below
+        sweep_pair<N, R, U>(P, stash, g, [&](int k, Real own, Real t, Real lown, Real lt) {
+            const Real e = e_reg(k);
+            const Real b = own * inv_dt + src;
+            Real res = src - e * own - c * t;
+            res = res - (e * lown + c * lt);
+            RD_PIN(res);
+            r[k] = res;
+            bb += (double)b * (double)b;
+            rr += (double)res * (double)res;
+            RD_PIN(bb);
+            RD_PIN(rr);
+        });
+        __syncthreads();  // every stencil read of P and of the stash is done
+#pragma unroll U
+        for (int k = 0; k < R; ++k)
+            stash[g.idx(k)] = Sr[k];
+    } else {
 #pragma unroll U
     for (int k = 0; k < R; ++k) {
         P[g.idx(k)] = hi[k];
@@ -212,7 +283,6 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
 
     // r0 = b - A x = src - e x - c t(x): the 1/dt terms cancel exactly, so
     // r0 (the scaled time derivative) keeps full relative precision.
-    double bb = 0.0, rr = 0.0;
     sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
         const Real b = own * inv_dt + src;
         Real res = src - e_at(k) * own - c * t;
@@ -238,9 +308,11 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             RD_PIN(rr);
         });
     }
+    }
     bool rr_pending = false;
     if (H && pred) {
-        __syncthreads();  // every stencil read of P is done
+        if constexpr (!kFuse)
+            __syncthreads();  // every stencil read of P is done
         copy_to_lds<N, R, U, kLds>(H + g.off(), P, g);
         __syncthreads();
         double rw = 0.0, ww = 0.0;
@@ -499,7 +571,26 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
         const bool pred_u = s > 0 && last_u > 0;
         const bool pred_v = s > 0 && last_v > 0;
         const int itu0 = itu, itv0 = itv;
-        if constexpr (kLds) {
+        if constexpr (kLds && comp) {
+            // FP32: each solve parks the other field itself, after its fused
+            // residual pass has used the stash for the low part
+            LdsArr<Real, N> sv{stash + g.idx(0)};
+            st = cg_solve<N, R, U, NW, kLds, 0, true>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam,
+                                                      rtol2, maxit, P, lo_u, h_u, pred_u, red, g,
+                                                      itu, &xv, stash);
+#pragma unroll U
+            for (int k = 0; k < R; ++k)
+                xv[k] = sv[k];
+            if (st)
+                break;
+            store_increment<N, R, U>(d, h_u, g);
+            st = cg_solve<N, R, U, NW, kLds, 1, true>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam,
+                                                      rtol2, maxit, P, lo_v, h_v, pred_v, red, g,
+                                                      itv, &xu, stash);
+#pragma unroll U
+            for (int k = 0; k < R; ++k)
+                xu[k] = sv[k];
+        } else if constexpr (kLds) {
             LdsArr<Real, N> sv{stash + g.idx(0)};
 #pragma unroll U
             for (int k = 0; k < R; ++k)
