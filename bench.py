@@ -67,11 +67,12 @@ PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed); FLOP/s
 FLOP_CG_ITER = 20.0
 FLOP_SETUP = 38.0
 # HBM bytes of the fused solve kernel from two rocprofv3 PMC passes over the
-# timed step of `bench.py --steps 1 --warmup 0 --no-da --no-cpu-baseline`
-# (3831 solves): FETCH_SIZE 3 690 661 513 KiB x 2.00 + WRITE_SIZE
-# 7 467 109 936 KiB x 1.00 (factors from a 256 MiB copy), per solve-step.
-# Valid only for the kernel version and tile it was measured on.
-MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 496110.52445001306}
+# timed step of `bench.py --steps 1 --warmup 0 --no-da --no-cpu-baseline
+# --no-mixed` (3831 solves): FETCH_SIZE 3 500 968 941 KiB x 2.00 +
+# WRITE_SIZE 7 460 487 633 KiB x 1.00 (factors from a 256 MiB copy), per
+# solve-step.  Valid only for the kernel version and tile it was measured on
+# (the one-pass residual of hi and lo).
+MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 483175.7271769251}
 
 
 def log(msg):
@@ -359,6 +360,75 @@ def mixed_leg(args, log):
             "initial_failed_solves_per_class": failed0}
 
 
+def precision_256_leg(args, log):
+    """FP32 against FP64 at 256^2: 16 prior draws solved to T = 2 on the
+    stationary domain by the FP32 path (cooperative tile, rtol 1e-7) and by
+    the FP64 path (streamed tile, rtol 1e-10); relative L2 of the final u
+    and v fields.  The FP64 reference runs in chunks of steps, each
+    restarting from the previous chunk's FP64 fields (exact on a stationary
+    domain: a step depends only on the current fields), as two 8-class
+    problems per chunk (one class per draw)."""
+    import torch
+    from paper_1605_04718_amd import inputs
+    from paper_1605_04718_amd.api import Grid, Problem
+    n, m = 256, 16
+    n_steps = int(round(T_FINAL / TAU))
+    chunk = args.p256_chunk
+    u0, v0 = inputs.initial_fields(n, THETA_TRUE[0], THETA_TRUE[1])
+    phi = inputs.box_draws(m, LO, HI, seed=inputs.SEED_DATASET)
+    th = torch.tensor(inputs.to_natural(phi), dtype=torch.float64, device="cuda")
+    p32 = Problem([Grid(n=n, u0=u0, v0=v0)], TAU, n_steps, CG_RTOL, cg_maxit=CG_MAXIT_MIXED,
+                  max_batch=m)
+    torch.cuda.synchronize()
+    t = time.time()
+    u32, v32, st32, _ = p32.forward_solve(th)
+    torch.cuda.synchronize()
+    t32 = time.time() - t
+    u32, v32, st32 = u32.double().cpu().numpy(), v32.double().cpu().numpy(), st32.cpu().numpy()
+    p32.close()
+    log(f"precision 256: FP32 path {t32:.1f} s")
+    U = [u0.ravel().copy() for _ in range(m)]
+    V = [v0.ravel().copy() for _ in range(m)]
+    st64 = np.zeros(m, dtype=np.int64)
+    t = time.time()
+    for c0 in range(0, n_steps, chunk):
+        steps = min(chunk, n_steps - c0)
+        for h0 in range(0, m, 8):
+            ks = list(range(h0, min(h0 + 8, m)))
+            grids = [Grid(n=n, u0=U[k].reshape(n, n), v0=V[k].reshape(n, n)) for k in ks]
+            p = Problem(grids, TAU, steps, 1e-10, precision=1, max_batch=len(ks))
+            gid = torch.arange(len(ks), dtype=torch.int32, device="cuda")
+            u, v, st, _ = p.forward_solve(th[ks[0]:ks[-1] + 1].contiguous(), grid_id=gid)
+            torch.cuda.synchronize()
+            u, v, st = u.cpu().numpy(), v.cpu().numpy(), st.cpu().numpy()
+            for j, k in enumerate(ks):
+                U[k], V[k] = u[j, :n * n].copy(), v[j, :n * n].copy()
+                st64[k] |= int(st[j])
+            p.close()
+            log(f"precision 256: FP64 reference draws {ks[0]}-{ks[-1]}, {c0 + steps}/{n_steps} "
+                f"steps, {time.time() - t:.1f} s")
+    t64 = time.time() - t
+    ok = [k for k in range(m) if st32[k] == 0 and st64[k] == 0]
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    eu = [rel(u32[k, :n * n], U[k]) for k in ok]
+    ev = [rel(v32[k, :n * n], V[k]) for k in ok]
+    return {
+        "workload": f"{m} prior draws, 256x256, stationary, T=2 ({n_steps} steps of 2.5e-4): "
+                    "FP32 path (compensated fields, cooperative tile, CG rtol 1e-7) against FP64 "
+                    f"(streamed tile, CG rtol 1e-10, {chunk}-step chunks)",
+        "solved_both": len(ok), "failed_fp32": int((st32 != 0).sum()),
+        "failed_fp64": int((st64 != 0).sum()),
+        "rel_l2_u": {"median": float(np.median(eu)), "max": float(np.max(eu)),
+                     "per_draw": eu},
+        "rel_l2_v": {"median": float(np.median(ev)), "max": float(np.max(ev)),
+                     "per_draw": ev},
+        "fp32_seconds": t32, "fp64_seconds": t64,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +449,10 @@ def main():
                     help="timed steps of the uneven workload")
     ap.add_argument("--mixed-scale", type=float, default=1.0,
                     help="fraction of the 4095 chains of the uneven workload")
+    ap.add_argument("--precision-256", action="store_true",
+                    help="also compare the FP32 and FP64 paths at 256^2 (16 prior draws, T = 2)")
+    ap.add_argument("--p256-chunk", type=int, default=1000,
+                    help="steps per FP64 reference call of --precision-256")
     ap.add_argument("--stationary", action="store_true",
                     help="also run plain vs delayed acceptance near stationarity (ESS/s)")
     ap.add_argument("--st-chains", type=int, default=1024)
@@ -531,6 +605,8 @@ def main():
 
     if not args.no_mixed:
         line["mixed"] = mixed_leg(args, log)
+    if args.precision_256:
+        line["precision_256"] = precision_256_leg(args, log)
     if args.stationary:
         line["stationary"] = stationary_leg(args, u0, v0, y, sigma, log)
 
