@@ -384,7 +384,9 @@ def precision_256_leg(args, log):
     u32, v32, st32, _ = p32.forward_solve(th)
     torch.cuda.synchronize()
     t32 = time.time() - t
-    u32, v32, st32 = u32.double().cpu().numpy(), v32.double().cpu().numpy(), st32.cpu().numpy()
+    u32 = u32.double().cpu().numpy().reshape(m, -1)
+    v32 = v32.double().cpu().numpy().reshape(m, -1)
+    st32 = st32.cpu().numpy()
     p32.close()
     log(f"precision 256: FP32 path {t32:.1f} s")
     U = [u0.ravel().copy() for _ in range(m)]
@@ -400,7 +402,9 @@ def precision_256_leg(args, log):
             gid = torch.arange(len(ks), dtype=torch.int32, device="cuda")
             u, v, st, _ = p.forward_solve(th[ks[0]:ks[-1] + 1].contiguous(), grid_id=gid)
             torch.cuda.synchronize()
-            u, v, st = u.cpu().numpy(), v.cpu().numpy(), st.cpu().numpy()
+            u = u.cpu().numpy().reshape(len(ks), -1)
+            v = v.cpu().numpy().reshape(len(ks), -1)
+            st = st.cpu().numpy()
             for j, k in enumerate(ks):
                 U[k], V[k] = u[j, :n * n].copy(), v[j, :n * n].copy()
                 st64[k] |= int(st[j])
