@@ -5,10 +5,13 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 Sec. 2, Algorithm 1: draw a proposal from a symmetric kernel k(x_k, .),
 accept it with probability min(1, exp(Phi(x_k) - Phi(x_bar))), otherwise
 stay.  Proposals are Gaussian random-walk steps in the sampling coordinates
-phi = (a, b, ln gamma, ln d); the prior is uniform on a box in phi, so inside
-the box the prior ratio is 1 (the acceptance formula of Algorithm 1 is exact)
-and a proposal outside the box has zero posterior density and is rejected
-without evaluating Phi.
+phi = (a, b, ln gamma, ln d); the default prior is uniform on a box in phi,
+so inside the box the prior ratio is 1 (the acceptance formula of Algorithm
+1 is exact) and a proposal outside the box has zero posterior density and is
+rejected without evaluating Phi.  The priors of Sec. 3.1.2 (Turing-space
+support, Case 2; log-normal gamma and d, Case 3) add the prior ratio
+pi(x_bar) / pi(x_k) to the acceptance probability (the general
+Metropolis-Hastings ratio for a symmetric kernel).
 
 Random numbers follow the sampler's counter-based contract (Philox4x32-10,
 key = (chain, seed), counter = (step, purpose, block)):
@@ -57,30 +60,94 @@ def in_box(phi, lo, hi) -> bool:
     return all(lo[i] <= phi[i] <= hi[i] for i in range(4))
 
 
-def rwm_step(phi, loglik, seed, chain, step, lo, hi, step_sd, free_mask, loglik_fn):
-    """One step of Algorithm 1 for one chain.
+# --------------------------------------------------------------------------
+# Priors beyond the uniform box (Sec. 3.1.2, Cases 2-4)
+
+class Prior:
+    """Prior on the sampling coordinates phi = (a, b, ln gamma, ln d).
+
+    kinds[i] = 0: uniform on [lo[i], hi[i]] (Case 1);
+    kinds[i] = 1: normal N(mean[i], sd[i]^2) in phi_i, i.e. log-normal in
+    gamma or d (Case 3), with no bound;
+    turing: the support is also restricted to the Turing space of
+    eq. (turing) at the homogeneous steady state, with d = exp(phi_3) (Case
+    2: uniform on the Turing space)."""
+
+    def __init__(self, kinds=(0, 0, 0, 0), mean=(0.0,) * 4, sd=(1.0,) * 4, turing=False):
+        self.kinds = tuple(int(k) for k in kinds)
+        self.mean = tuple(float(m) for m in mean)
+        self.sd = tuple(float(x) for x in sd)
+        self.turing = bool(turing)
+
+
+def turing_space(a, b, d) -> bool:
+    """The four inequalities of eq. (turing) for the activator-depleted
+    kinetics at (u*, v*) = (a + b, b / (a + b)^2)."""
+    s = a + b
+    tr = (b - a) / s - s * s
+    det = s * s
+    dfg = d * ((b - a) / s) - s * s
+    disc = dfg * dfg - 4.0 * d * det
+    return tr < 0.0 and det > 0.0 and dfg > 0.0 and disc > 0.0
+
+
+def prior_quad(phi, prior) -> float:
+    """Sum over normal coordinates of (phi_i - mean_i)^2 / (2 sd_i^2), in
+    index order: minus the log prior density up to a constant."""
+    acc = 0.0
+    for i in range(4):
+        if prior.kinds[i] == 1:
+            q = (float(phi[i]) - prior.mean[i]) / prior.sd[i]
+            acc = acc + 0.5 * (q * q)
+    return acc
+
+
+def in_support(phi, lo, hi, prior=None) -> bool:
+    """Zero prior density outside: the box on uniform coordinates, and the
+    Turing space when the prior asks for it."""
+    for i in range(4):
+        if (prior is None or prior.kinds[i] == 0) and not (lo[i] <= phi[i] <= hi[i]):
+            return False
+    if prior is not None and prior.turing:
+        return turing_space(float(phi[0]), float(phi[1]), math.exp(float(phi[3])))
+    return True
+
+
+def log_prior_ratio(phi, prop, prior=None) -> float:
+    """log pi(prop) - log pi(phi) on the support (0 for the uniform prior)."""
+    if prior is None or not any(k == 1 for k in prior.kinds):
+        return 0.0
+    return prior_quad(phi, prior) - prior_quad(prop, prior)
+
+
+def rwm_step(phi, loglik, seed, chain, step, lo, hi, step_sd, free_mask, loglik_fn,
+             prior=None, chol=None):
+    """One step of Algorithm 1 for one chain; with a non-uniform prior the
+    log acceptance ratio gains log pi(prop) - log pi(phi).
 
     Returns (phi_next, loglik_next, accepted, solved)."""
-    prop = propose(phi, seed, chain, step, step_sd, free_mask)
-    if not in_box(prop, lo, hi):
+    prop = propose(phi, seed, chain, step, step_sd, free_mask, chol)
+    if not in_support(prop, lo, hi, prior):
         return np.array(phi, dtype=np.float64), loglik, False, False
     ll_prop = float(loglik_fn(prop))
     u = uniform1(seed, chain, step, PURPOSE_ACCEPT)
-    log_alpha = loglik - ll_prop
+    log_alpha = (loglik - ll_prop) + log_prior_ratio(phi, prop, prior)
     if math.log(u) < log_alpha:
         return prop, ll_prop, True, True
     return np.array(phi, dtype=np.float64), loglik, False, True
 
 
-def rwm_batch_step(phis, logliks, seed, step, lo, hi, step_sd, free_mask, loglik_batch_fn):
+def rwm_batch_step(phis, logliks, seed, step, lo, hi, step_sd, free_mask, loglik_batch_fn,
+                   prior=None, chol=None):
     """Algorithm 1 applied to every chain; loglik_batch_fn maps [m,4] -> [m].
 
     Returns (phis, logliks, accepted[bool], solved[bool])."""
     phis = np.array(phis, dtype=np.float64)
     logliks = np.array(logliks, dtype=np.float64)
     C = phis.shape[0]
-    props = np.stack([propose(phis[c], seed, c, step, step_sd, free_mask) for c in range(C)])
-    inside = np.array([in_box(props[c], lo, hi) for c in range(C)])
+    props = np.stack([propose(phis[c], seed, c, step, step_sd, free_mask, chol)
+                      for c in range(C)])
+    inside = np.array([in_support(props[c], lo, hi, prior) for c in range(C)])
     ll_prop = np.full(C, np.inf)
     if inside.any():
         ll_prop[inside] = loglik_batch_fn(props[inside])
@@ -89,7 +156,7 @@ def rwm_batch_step(phis, logliks, seed, step, lo, hi, step_sd, free_mask, loglik
         if not inside[c]:
             continue
         u = uniform1(seed, c, step, PURPOSE_ACCEPT)
-        if math.log(u) < logliks[c] - ll_prop[c]:
+        if math.log(u) < (logliks[c] - ll_prop[c]) + log_prior_ratio(phis[c], props[c], prior):
             accepted[c] = True
     phis[accepted] = props[accepted]
     logliks[accepted] = ll_prop[accepted]
@@ -97,17 +164,18 @@ def rwm_batch_step(phis, logliks, seed, step, lo, hi, step_sd, free_mask, loglik
 
 
 def da_step(phi, loglik, loglik_sur, seed, chain, step, lo, hi, step_sd, free_mask,
-            loglik_fn, surrogate_fn):
-    """One delayed-acceptance step for one chain.
+            loglik_fn, surrogate_fn, prior=None):
+    """One delayed-acceptance step for one chain.  The prior ratio enters
+    the first stage (it cancels from the second).
 
     Returns (phi, loglik, loglik_sur, accepted1, accepted, solved)."""
     prop = propose(phi, seed, chain, step, step_sd, free_mask)
     keep = (np.array(phi, dtype=np.float64), loglik, loglik_sur)
-    if not in_box(prop, lo, hi):
+    if not in_support(prop, lo, hi, prior):
         return (*keep, False, False, False)
     sur_prop = float(surrogate_fn(prop))
     u1 = uniform1(seed, chain, step, PURPOSE_STAGE1)
-    if not math.log(u1) < loglik_sur - sur_prop:
+    if not math.log(u1) < (loglik_sur - sur_prop) + log_prior_ratio(phi, prop, prior):
         return (*keep, False, False, False)
     ll_prop = float(loglik_fn(prop))
     u2 = uniform1(seed, chain, step, PURPOSE_ACCEPT)
