@@ -107,7 +107,22 @@ typedef struct {
                                       the free coordinates (a correlated Gaussian
                                       step, still symmetric) and step[] is not
                                       used; all zero: phi'_i = phi_i + step_i z_i */
+    /* Prior (Sec. 3.1.2, Cases 1-4).  prior_kind[i] = RD_PRIOR_UNIFORM:
+     * uniform on [lo[i], hi[i]] (Case 1; zero-initialised descriptors get
+     * this); RD_PRIOR_NORMAL: N(prior_mean[i], prior_sd[i]^2) in sampling
+     * coordinate i without a bound, i.e. log-normal in gamma or d (Case 3).
+     * turing_support = 1: the support is also restricted to the Turing
+     * space of eq. (turing) at (a, b, d = exp(phi_3)) (Case 2).  The
+     * acceptance ratio gains pi(proposal) / pi(state) (plain steps and the
+     * first delayed-acceptance stage; it cancels from the second); a
+     * proposal outside the support is rejected without a solve. */
+    int32_t prior_kind[4];
+    double prior_mean[4];
+    double prior_sd[4];            /* > 0 where prior_kind is RD_PRIOR_NORMAL */
+    int32_t turing_support;
 } rd_problem_desc;
+
+enum { RD_PRIOR_UNIFORM = 0, RD_PRIOR_NORMAL = 1 };
 
 /* Creates a problem: validates the description, uploads the initial fields
  * and data, sizes the workspace for max_batch items and picks the solver

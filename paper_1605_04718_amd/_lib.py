@@ -32,7 +32,8 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("n_grids", c_i32), ("grids", ctypes.POINTER(GridDesc)), ("dt", c_d),
                 ("n_steps", c_i32), ("cg_rtol", c_d), ("cg_maxit", c_i32), ("precision", c_i32),
                 ("free_mask", c_u32), ("lo", c_d * 4), ("hi", c_d * 4), ("step", c_d * 4),
-                ("max_batch", c_i32), ("prop_chol", c_d * 16)]
+                ("max_batch", c_i32), ("prop_chol", c_d * 16), ("prior_kind", c_i32 * 4),
+                ("prior_mean", c_d * 4), ("prior_sd", c_d * 4), ("turing_support", c_i32)]
 
 
 class Chains(ctypes.Structure):

@@ -51,9 +51,14 @@ class Problem:
 
     def __init__(self, grids, dt, n_steps, cg_rtol, *, precision=FP32, cg_maxit=0,
                  free_mask=0b1111, lo=(0, 0, 0, 0), hi=(1, 1, 1, 1), step=(0, 0, 0, 0),
-                 max_batch=4096, prop_chol=None):
+                 max_batch=4096, prop_chol=None, prior_kind=(0, 0, 0, 0),
+                 prior_mean=(0.0, 0.0, 0.0, 0.0), prior_sd=(1.0, 1.0, 1.0, 1.0),
+                 turing_support=False):
         """prop_chol: optional lower-triangular 4 x 4 factor L of a correlated
-        random-walk step (phi' = phi + L z); step is then unused."""
+        random-walk step (phi' = phi + L z); step is then unused.
+        prior_kind[i]: 0 uniform on [lo[i], hi[i]], 1 normal N(prior_mean[i],
+        prior_sd[i]^2) in sampling coordinate i (log-normal in gamma, d);
+        turing_support: restrict the support to the Turing space."""
         if isinstance(grids, Grid):
             grids = [grids]
         self.grids = list(grids)
@@ -93,6 +98,11 @@ class Problem:
         for i in range(4):
             d.lo[i], d.hi[i], d.step[i] = lo[i], hi[i], step[i]
         d.max_batch = max_batch
+        for i in range(4):
+            d.prior_kind[i] = int(prior_kind[i])
+            d.prior_mean[i] = float(prior_mean[i])
+            d.prior_sd[i] = float(prior_sd[i])
+        d.turing_support = int(bool(turing_support))
         if prop_chol is not None:
             L = np.asarray(prop_chol, dtype=np.float64).reshape(4, 4)
             for i in range(4):

@@ -298,11 +298,18 @@ SamplerArgs sampler_args(rd_problem *p, const rd_chains *c)
         if (p->desc.prop_chol[i] != 0.0)
             a.cfg.use_chol = 1;
     }
+    a.cfg.any_normal = 0;
     for (int i = 0; i < 4; ++i) {
         a.cfg.lo[i] = p->desc.lo[i];
         a.cfg.hi[i] = p->desc.hi[i];
         a.cfg.step[i] = p->desc.step[i];
+        a.cfg.prior_kind[i] = p->desc.prior_kind[i];
+        a.cfg.prior_mean[i] = p->desc.prior_mean[i];
+        a.cfg.prior_sd[i] = p->desc.prior_sd[i];
+        if (p->desc.prior_kind[i] == RD_PRIOR_NORMAL)
+            a.cfg.any_normal = 1;
     }
+    a.cfg.turing = p->desc.turing_support;
     a.phi = c->phi;
     a.loglik = c->loglik;
     a.loglik_sur = c->loglik_sur;
@@ -392,6 +399,16 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         for (int j = 0; j < 4; ++j)
             if ((j > i && desc->prop_chol[4 * i + j] != 0.0) || !std::isfinite(desc->prop_chol[4 * i + j]))
                 return fail(RD_EINVAL, "prop_chol must be finite and lower-triangular");
+    for (int i = 0; i < 4; ++i) {
+        if (desc->prior_kind[i] != RD_PRIOR_UNIFORM && desc->prior_kind[i] != RD_PRIOR_NORMAL)
+            return fail(RD_EINVAL, "prior_kind[%d] = %d is not a prior kind", i, desc->prior_kind[i]);
+        if (desc->prior_kind[i] == RD_PRIOR_NORMAL &&
+            (!std::isfinite(desc->prior_mean[i]) || !(desc->prior_sd[i] > 0.0) ||
+             !std::isfinite(desc->prior_sd[i])))
+            return fail(RD_EINVAL, "normal prior %d needs a finite mean and a positive s.d.", i);
+    }
+    if (desc->turing_support != 0 && desc->turing_support != 1)
+        return fail(RD_EINVAL, "turing_support must be 0 or 1");
     for (int g = 0; g < desc->n_grids; ++g) {
         const rd_grid_desc &gd = desc->grids[g];
         if (!tile_supported(gd.n, desc->precision, default_cpt(gd.n, desc->precision)))

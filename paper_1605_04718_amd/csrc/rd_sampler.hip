@@ -13,9 +13,45 @@ namespace rd {
 
 enum : uint32_t { kPurposeProposal = 0, kPurposeAccept = 1, kPurposeStage1 = 2 };
 
+// The four inequalities of eq. (turing) for the activator-depleted kinetics
+// at the homogeneous steady state (a + b, b / (a + b)^2).
+__device__ bool turing_space(double a, double b, double d)
+{
+    const double s = a + b;
+    const double tr = (b - a) / s - s * s;
+    const double det = s * s;
+    const double dfg = d * ((b - a) / s) - s * s;
+    const double disc = dfg * dfg - 4.0 * d * det;
+    return tr < 0.0 && det > 0.0 && dfg > 0.0 && disc > 0.0;
+}
+
+// Sum over normal-prior coordinates of (phi_i - mean_i)^2 / (2 sd_i^2), in
+// index order: minus the log prior density up to a constant.
+__device__ double prior_quad(const SamplerCfg &cfg, const double *phi)
+{
+    double acc = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        if (cfg.prior_kind[i] == 1) {
+            const double q = (phi[i] - cfg.prior_mean[i]) / cfg.prior_sd[i];
+            acc = acc + 0.5 * (q * q);
+        }
+    }
+    return acc;
+}
+
+// log pi(proposal) - log pi(state) of chain c on the support (0 for the
+// uniform prior).
+__device__ double log_prior_ratio(const SamplerArgs &a, int c)
+{
+    if (!a.cfg.any_normal)
+        return 0.0;
+    return prior_quad(a.cfg, a.phi + 4 * c) - prior_quad(a.cfg, a.phi_prop + 4 * c);
+}
+
 // phi' = phi + s .* z, or phi + L z with the proposal factor (free
-// coordinates), z ~ N(0, I); inside = every
-// coordinate within [lo, hi]; theta' = (a, b, exp(ln gamma), exp(ln d)).
+// coordinates), z ~ N(0, I); inside = in the prior's support (uniform
+// coordinates within [lo, hi]; with the Turing support, (a, b, d) in the
+// Turing space); theta' = (a, b, exp(ln gamma), exp(ln d)).
 __global__ void k_propose(SamplerArgs a)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,19 +77,24 @@ __global__ void k_propose(SamplerArgs a)
             }
             p[i] = p[i] + dz;
         }
-        in = in && (a.cfg.lo[i] <= p[i]) && (p[i] <= a.cfg.hi[i]);
+        if (a.cfg.prior_kind[i] == 0)
+            in = in && (a.cfg.lo[i] <= p[i]) && (p[i] <= a.cfg.hi[i]);
         a.phi_prop[4 * c + i] = p[i];
     }
+    const double d = exp(p[3]);
+    if (a.cfg.turing)
+        in = in && turing_space(p[0], p[1], d);
     if (a.theta_prop) {
         a.theta_prop[4 * c + 0] = p[0];
         a.theta_prop[4 * c + 1] = p[1];
         a.theta_prop[4 * c + 2] = exp(p[2]);
-        a.theta_prop[4 * c + 3] = exp(p[3]);
+        a.theta_prop[4 * c + 3] = d;
     }
     a.inside[c] = in ? 1 : 0;
 }
 
-// Accept iff log U < Phi(phi) - Phi(phi'), U from purpose 1; then record.
+// Accept iff log U < [Phi(phi) - Phi(phi')] + [log pi(phi') - log pi(phi)],
+// U from purpose 1; then record.
 __global__ void k_accept(SamplerArgs a)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,7 +105,7 @@ __global__ void k_accept(SamplerArgs a)
     if (a.inside[c]) {
         const U32x4 w = stream_block(a.seed, (uint32_t)c, step, kPurposeAccept, 0);
         const double u = unit_open(w.x, w.y);
-        acc = log(u) < a.loglik[c] - a.loglik_prop[c];
+        acc = log(u) < (a.loglik[c] - a.loglik_prop[c]) + log_prior_ratio(a, c);
         if (a.n_solves)
             a.n_solves[c] += 1;
         if (a.cg_iters && a.iters) {
@@ -88,8 +129,9 @@ __global__ void k_accept(SamplerArgs a)
     }
 }
 
-// Delayed acceptance, first stage: log U1 < Phi~(phi) - Phi~(phi'), U1 from
-// purpose 2.  Writes need[c] (solve the proposal) and counts stage-1 accepts.
+// Delayed acceptance, first stage: log U1 < [Phi~(phi) - Phi~(phi')] +
+// [log pi(phi') - log pi(phi)], U1 from purpose 2.  Writes need[c] (solve
+// the proposal) and counts stage-1 accepts.
 __global__ void k_da_stage1(SamplerArgs a)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,7 +142,7 @@ __global__ void k_da_stage1(SamplerArgs a)
     if (a.inside[c]) {
         const U32x4 w = stream_block(a.seed, (uint32_t)c, step, kPurposeStage1, 0);
         const double u = unit_open(w.x, w.y);
-        acc1 = log(u) < a.loglik_sur[c] - a.loglik_sur_prop[c];
+        acc1 = log(u) < (a.loglik_sur[c] - a.loglik_sur_prop[c]) + log_prior_ratio(a, c);
     }
     a.need[c] = acc1 ? 1 : 0;
     if (acc1 && a.n_accept1)

@@ -10,6 +10,10 @@ struct SamplerCfg {
     int use_chol;          // proposal step L z instead of step .* z
     double lo[4], hi[4], step[4];
     double chol[16];       // lower-triangular L, row-major
+    int prior_kind[4];     // 0 uniform on [lo, hi], 1 normal in the sampling coordinate
+    double prior_mean[4], prior_sd[4];
+    int any_normal;        // some coordinate has a normal prior
+    int turing;            // support restricted to the Turing space
 };
 
 struct SamplerArgs {
