@@ -69,6 +69,9 @@ def lib():
         L.orc_uniform1.argtypes = [c_u32, c_u32, c_u64, c_u32]
         L.orc_uniform1.restype = c_d
         L.orc_uniforms4.argtypes = [c_u32, c_u32, c_u64, c_u32, dp]
+        L.orc_normals4_at.argtypes = [c_u32, c_u32, c_u64, c_u32, c_u32, dp]
+        L.orc_uniform_at.argtypes = [c_u32, c_u32, c_u64, c_u32, c_u32]
+        L.orc_uniform_at.restype = c_d
         _lib = L
     return _lib
 
@@ -203,6 +206,19 @@ def normals4(seed, chain, step, purpose):
 
 def uniform1(seed, chain, step, purpose) -> float:
     return lib().orc_uniform1(int(seed) & 0xFFFFFFFF, int(chain), int(step), int(purpose))
+
+
+def normals4_at(seed, chain, step, purpose, block0):
+    """Four normals from blocks block0, block0 + 1 (normals4 is block0 = 0)."""
+    z = np.zeros(4)
+    lib().orc_normals4_at(int(seed) & 0xFFFFFFFF, int(chain), int(step), int(purpose),
+                          int(block0), _d(z))
+    return z
+
+
+def uniform_at(seed, chain, step, purpose, block) -> float:
+    return lib().orc_uniform_at(int(seed) & 0xFFFFFFFF, int(chain), int(step), int(purpose),
+                                int(block))
 
 
 def uniforms4(seed, chain, step, purpose):

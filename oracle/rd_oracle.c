@@ -419,3 +419,28 @@ void orc_uniforms4(uint32_t seed, uint32_t chain, uint64_t step, uint32_t purpos
         uo[2 * blk + 1] = orc_uniform_from_words(w[2], w[3]);
     }
 }
+
+/* Four standard normals from blocks blk0 and blk0 + 1 of a stream (the
+ * draws of orc_normals4 when blk0 = 0). */
+void orc_normals4_at(uint32_t seed, uint32_t chain, uint64_t step, uint32_t purpose, uint32_t blk0,
+                     double z[4])
+{
+    for (uint32_t b = 0; b < 2; ++b) {
+        uint32_t w[4];
+        stream_words(seed, chain, step, purpose, blk0 + b, w);
+        double u1 = orc_uniform_from_words(w[0], w[1]);
+        double u2 = orc_uniform_from_words(w[2], w[3]);
+        double rad = sqrt(-2.0 * log(u1));
+        double ang = 6.283185307179586476925286766559 * u2; /* 2 pi */
+        z[2 * b] = rad * cos(ang);
+        z[2 * b + 1] = rad * sin(ang);
+    }
+}
+
+/* One uniform in (0,1) from block blk of a stream. */
+double orc_uniform_at(uint32_t seed, uint32_t chain, uint64_t step, uint32_t purpose, uint32_t blk)
+{
+    uint32_t w[4];
+    stream_words(seed, chain, step, purpose, blk, w);
+    return orc_uniform_from_words(w[0], w[1]);
+}

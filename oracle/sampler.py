@@ -31,11 +31,14 @@ import math
 
 import numpy as np
 
-from . import normals4, uniform1
+from . import normals4, normals4_at, uniform1, uniform_at
 
 PURPOSE_PROPOSAL = 0
 PURPOSE_ACCEPT = 1
 PURPOSE_STAGE1 = 2
+PURPOSE_PMH_AUX = 6       # parallel MH: the auxiliary point
+PURPOSE_PMH_PROP = 7      # parallel MH: proposal j from blocks 2j, 2j + 1
+PURPOSE_PMH_RESAMPLE = 8  # parallel MH: uniform of draw n from block n
 
 
 def propose(phi, seed, chain, step, step_sd, free_mask, chol=None):
@@ -183,3 +186,105 @@ def da_step(phi, loglik, loglik_sur, seed, chain, step, lo, hi, step_sd, free_ma
     if math.log(u2) < log_alpha2:
         return prop, ll_prop, sur_prop, True, True, True
     return (*keep, True, False, True)
+
+
+# --------------------------------------------------------------------------
+# Parallel Metropolis-Hastings (Sec. 2, Algorithm 2)
+#
+# N proposals are evaluated at once, the acceptance probabilities of the
+# N + 1 points (the N proposals and the present state x_k) are the
+# stationary distribution of the transition matrix
+#   A(i, j) = min(1, r(x_i, x_j)) / N  (j != i),  A(i, i) = 1 - sum_{j != i} A(i, j),
+#   r(x, y) = exp(Phi(x) - Phi(y))  (times pi0(y) / pi0(x) for a non-uniform prior),
+# and N draws from that distribution are the next N states.  As printed the
+# proposals are drawn around x_k; here they are drawn around an auxiliary
+# point z ~ k(x_k, .) (Calderhead, PNAS 111(49), 2014, the construction the
+# algorithm cites), for which A with this r leaves the posterior invariant
+# when k is symmetric.  The last draw is the present state of the next step.
+
+
+def pmh_points(phi, seed, chain, step, n_prop, step_sd, free_mask, chol=None):
+    """[n_prop + 1, 4]: row 0 the present state, rows 1..N the proposals
+    (z = x_k + dz with normals of purpose 6; x_j = z + dz_j with normals of
+    purpose 7, blocks 2(j-1), 2(j-1) + 1)."""
+
+    def move(x, z):
+        y = np.array(x, dtype=np.float64).copy()
+        for i in range(4):
+            if (free_mask >> i) & 1:
+                if chol is not None:
+                    dz = 0.0
+                    for j in range(i + 1):
+                        dz = dz + float(chol[i][j]) * float(z[j])
+                else:
+                    dz = step_sd[i] * z[i]
+                y[i] = y[i] + dz
+        return y
+
+    aux = move(phi, normals4_at(seed, chain, step, PURPOSE_PMH_AUX, 0))
+    pts = [np.array(phi, dtype=np.float64)]
+    for j in range(n_prop):
+        pts.append(move(aux, normals4_at(seed, chain, step, PURPOSE_PMH_PROP, 2 * j)))
+    return np.stack(pts)
+
+
+def pmh_matrix(logw):
+    """A of Algorithm 2 from the log target densities of the N + 1 points
+    (-inf outside the support): A(i, j) = min(1, w_j / w_i) / N."""
+    logw = np.asarray(logw, dtype=np.float64)
+    m = len(logw) - 1
+    A = np.zeros((m + 1, m + 1))
+    for i in range(m + 1):
+        for j in range(m + 1):
+            if j == i:
+                continue
+            if logw[i] == -np.inf:
+                ratio = 1.0 if logw[j] > -np.inf else 0.0
+            else:
+                ratio = min(1.0, math.exp(min(0.0, logw[j] - logw[i])))
+            A[i, j] = ratio / m
+        A[i, i] = 1.0 - A[i].sum()
+    return A
+
+
+def stationary(A):
+    """p with p A = p and sum p = 1 (one equation of (A^T - I) p = 0
+    replaced by the normalisation, dense solve)."""
+    n = A.shape[0]
+    M = A.T - np.eye(n)
+    M[-1, :] = 1.0
+    rhs = np.zeros(n)
+    rhs[-1] = 1.0
+    return np.linalg.solve(M, rhs)
+
+
+def pmh_draw(p, u) -> int:
+    """Smallest index whose running sum of p (in index order) exceeds u."""
+    acc = 0.0
+    for i, pi in enumerate(p):
+        acc = acc + pi
+        if u < acc:
+            return i
+    return len(p) - 1 - int(np.argmax(np.asarray(p)[::-1] > 0))
+
+
+def pmh_step(phi, loglik, seed, chain, step, n_prop, lo, hi, step_sd, free_mask, loglik_fn,
+             prior=None, chol=None):
+    """One step of Algorithm 2 for one chain.
+
+    Returns (draws [N, 4], draw logliks [N], draw indices [N], points
+    [N+1, 4], point logliks [N+1], stationary p [N+1]); the last draw is the
+    next present state."""
+    pts = pmh_points(phi, seed, chain, step, n_prop, step_sd, free_mask, chol)
+    ll = np.full(n_prop + 1, np.inf)
+    ll[0] = loglik
+    for j in range(1, n_prop + 1):
+        if in_support(pts[j], lo, hi, prior):
+            ll[j] = float(loglik_fn(pts[j]))
+    logw = -ll
+    if prior is not None and any(k == 1 for k in prior.kinds):
+        logw = np.array([logw[j] - prior_quad(pts[j], prior) for j in range(n_prop + 1)])
+    p = stationary(pmh_matrix(logw))
+    idx = np.array([pmh_draw(p, uniform_at(seed, chain, step, PURPOSE_PMH_RESAMPLE, n))
+                    for n in range(n_prop)])
+    return pts[idx], ll[idx], idx, pts, ll, p
