@@ -225,6 +225,35 @@ int32_t propose_batch(rd_problem *p, rd_chains *chains, double *phi_prop, int32_
 int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *phi_prop,
                      const int32_t *inside, const double *loglik_prop, void *stream);
 
+/* ---- parallel Metropolis-Hastings (Sec. 2, Algorithm 2) -----------------
+ * One step of a chain evaluates Phi at N proposals at once and produces N
+ * states: the stationary distribution of the (N+1)-state transition matrix
+ * A(i, j) = min(1, r(x_i, x_j)) / N over the proposals and the present
+ * state, r(x, y) = exp(Phi(x) - Phi(y)) pi0(y) / pi0(x), gives the
+ * probabilities of N draws.  As printed the proposals are drawn around the
+ * present state; here they are drawn around an auxiliary point z ~ k(x, .)
+ * (Calderhead's construction, which the algorithm cites), for which A leaves
+ * the posterior invariant with this symmetric random-walk kernel.  Random
+ * numbers: purpose 6 (z), 7 (proposal j: blocks 2j, 2j+1), 8 (draw n:
+ * block n).  The N draws fill trace rows chains->step .. chains->step + N - 1,
+ * the last draw is the next present state, chains->step advances by N,
+ * n_accept counts draws other than the present state and n_solves the
+ * proposals solved.  1 <= n_prop <= 256 and n_chains * n_prop <= max_batch.
+ *
+ * pmh_step_batch: n_iter steps with Phi from this library's fused solve
+ * (n_chains * n_prop items per launch).  pmh_propose_batch and
+ * pmh_resample_batch: the two halves around an external Phi; proposals are
+ * dev float64 [n_chains * n_prop][4] (item c * n_prop + j), inside and
+ * loglik_prop dev [n_chains * n_prop]; pmh_resample_batch advances
+ * chains->step by n_prop.  Errors: RD_EINVAL. */
+int32_t pmh_step_batch(rd_problem *p, rd_chains *chains, int32_t n_prop, int32_t n_iter,
+                       void *stream);
+int32_t pmh_propose_batch(rd_problem *p, rd_chains *chains, int32_t n_prop, double *phi_prop,
+                          int32_t *inside, void *stream);
+int32_t pmh_resample_batch(rd_problem *p, rd_chains *chains, int32_t n_prop,
+                           const double *phi_prop, const int32_t *inside,
+                           const double *loglik_prop, void *stream);
+
 /* ---- surrogate (first stage of delayed acceptance) ----------------------
  * An MLP 4 -> width x depth (GELU) -> (n/ds)^2 maps the sampling coordinates
  * (scaled to [-1, 1] on the prior box) to the block-mean-downsampled u field

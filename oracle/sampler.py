@@ -284,7 +284,11 @@ def pmh_step(phi, loglik, seed, chain, step, n_prop, lo, hi, step_sd, free_mask,
     logw = -ll
     if prior is not None and any(k == 1 for k in prior.kinds):
         logw = np.array([logw[j] - prior_quad(pts[j], prior) for j in range(n_prop + 1)])
-    p = stationary(pmh_matrix(logw))
-    idx = np.array([pmh_draw(p, uniform_at(seed, chain, step, PURPOSE_PMH_RESAMPLE, n))
-                    for n in range(n_prop)])
+    if not np.any(np.isfinite(logw)):
+        p = np.zeros(n_prop + 1)  # no point has positive density: stay
+        idx = np.zeros(n_prop, dtype=np.int64)
+    else:
+        p = stationary(pmh_matrix(logw))
+        idx = np.array([pmh_draw(p, uniform_at(seed, chain, step, PURPOSE_PMH_RESAMPLE, n))
+                        for n in range(n_prop)])
     return pts[idx], ll[idx], idx, pts, ll, p

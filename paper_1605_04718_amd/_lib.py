@@ -53,6 +53,9 @@ SYMBOLS = {
     "mcmc_step_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_i32, c_i32, c_vp]),
     "propose_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_vp, c_vp, c_vp]),
     "accept_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_vp, c_vp, c_vp, c_vp]),
+    "pmh_step_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_i32, c_i32, c_vp]),
+    "pmh_propose_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_i32, c_vp, c_vp, c_vp]),
+    "pmh_resample_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_i32, c_vp, c_vp, c_vp, c_vp]),
     "surrogate_create": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_u32]),
     "downsample_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "surrogate_set_scaling": (c_i32, [c_vp, c_vp, c_vp, c_d, c_vp]),

@@ -190,6 +190,33 @@ class Problem:
                                  _ptr(loglik_prop), _stream(stream)), "accept_batch")
         chains.step = int(c.step)
 
+    # -- parallel Metropolis-Hastings (Algorithm 2) ------------------------
+    def pmh_step(self, chains: "ChainState", n_prop, n_iter=1, stream=None):
+        """n_iter steps of Algorithm 2 (N = n_prop proposals per chain, N
+        draws each) with Phi from the library's solve."""
+        c = chains.struct()
+        check(lib().pmh_step_batch(self.h, ctypes.byref(c), int(n_prop), int(n_iter),
+                                   _stream(stream)), "pmh_step_batch")
+        chains.step = int(c.step)
+
+    def pmh_propose(self, chains: "ChainState", n_prop, stream=None):
+        """The N proposals of every chain: ([n * N, 4] float64, [n * N] int32)."""
+        n = chains.n
+        dev = chains.phi.device
+        prop = torch.empty((n * n_prop, 4), dtype=torch.float64, device=dev)
+        inside = torch.empty(n * n_prop, dtype=torch.int32, device=dev)
+        c = chains.struct()
+        check(lib().pmh_propose_batch(self.h, ctypes.byref(c), int(n_prop), _ptr(prop),
+                                      _ptr(inside), _stream(stream)), "pmh_propose_batch")
+        return prop, inside
+
+    def pmh_resample(self, chains: "ChainState", n_prop, prop, inside, loglik_prop, stream=None):
+        c = chains.struct()
+        check(lib().pmh_resample_batch(self.h, ctypes.byref(c), int(n_prop), _ptr(prop),
+                                       _ptr(inside), _ptr(loglik_prop), _stream(stream)),
+              "pmh_resample_batch")
+        chains.step = int(c.step)
+
     # -- surrogate (first stage of delayed acceptance) -------------------
     def surrogate_create(self, width=512, depth=4, out_side=32, seed=5):
         check(lib().surrogate_create(self.h, width, depth, out_side, seed), "surrogate_create")

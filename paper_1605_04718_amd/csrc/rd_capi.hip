@@ -88,6 +88,7 @@ struct rd_problem {
     double *ll_prop = nullptr;
     double *ll_sur_prop = nullptr;
     int *status_ws = nullptr;
+    int *pmh_gid = nullptr;   // [max_batch] item classes of a parallel-MH batch
     int *iters_ws = nullptr;
     uint64_t *ctr = nullptr;
     void *gws = nullptr;     // per-workgroup solve slots
@@ -485,6 +486,7 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     p->ll_sur_prop = (double *)dmalloc(p, sizeof(double) * B, &err);
     p->status_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->iters_ws = (int *)dmalloc(p, sizeof(int) * 2 * B, &err);
+    p->pmh_gid = (int *)dmalloc(p, sizeof(int) * B, &err);
     if (err != RD_OK) {
         destroy_problem(p);
         return err;
@@ -754,6 +756,100 @@ extern "C" int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *
     a.iters = nullptr;  // the caller's Phi did not come from this library's solve
     HIP_TRY(launch_accept(a, s));
     chains->step += 1;
+    return RD_OK;
+}
+
+static int32_t check_pmh(rd_problem *p, rd_chains *chains, int n_prop)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    int32_t r = check_chains(p, chains, RD_MODE_PLAIN);
+    if (r != RD_OK)
+        return r;
+    if (n_prop < 1 || n_prop > kMaxPmhProposals)
+        return fail(RD_EINVAL, "n_prop = %d outside [1, %d]", n_prop, kMaxPmhProposals);
+    if ((int64_t)chains->n_chains * n_prop > p->desc.max_batch)
+        return fail(RD_EINVAL, "n_chains * n_prop = %lld exceeds max_batch = %d",
+                    (long long)chains->n_chains * n_prop, p->desc.max_batch);
+    return RD_OK;
+}
+
+extern "C" int32_t pmh_step_batch(rd_problem *p, rd_chains *chains, int32_t n_prop,
+                                  int32_t n_iter, void *stream)
+{
+    int32_t r = check_pmh(p, chains, n_prop);
+    if (r != RD_OK)
+        return r;
+    if (n_iter < 0)
+        return fail(RD_EINVAL, "n_iter < 0");
+    for (auto &g : p->grids_host)
+        if (!g.y)
+            return fail(RD_EINVAL, "a grid class has no data y");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = chains->n_chains;
+    const int items = n * n_prop;
+    for (int k = 0; k < n_iter && n > 0; ++k) {
+        HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->trace_step0, s));
+        SamplerArgs a = sampler_args(p, chains);
+        a.phi_prop = p->phi_prop;
+        a.theta_prop = p->theta_prop;
+        a.inside = p->inside;
+        a.loglik_prop = p->ll_prop;
+        HIP_TRY(launch_pmh_propose(a, n_prop, s));
+        const int *gid = nullptr;
+        if (chains->grid_id && p->desc.n_grids > 1) {
+            HIP_TRY(launch_pmh_expand_gid(chains->grid_id, n, n_prop, p->pmh_gid, s));
+            gid = p->pmh_gid;
+        }
+        r = enqueue_solve(p, items, p->theta_prop, gid, p->inside, p->ll_prop, p->status_ws,
+                          p->iters_ws, nullptr, nullptr, s);
+        if (r != RD_OK)
+            return r;
+        HIP_TRY(launch_pmh_resample(a, n_prop, s));
+        chains->step += (uint64_t)n_prop;
+    }
+    return RD_OK;
+}
+
+extern "C" int32_t pmh_propose_batch(rd_problem *p, rd_chains *chains, int32_t n_prop,
+                                     double *phi_prop, int32_t *inside, void *stream)
+{
+    int32_t r = check_pmh(p, chains, n_prop);
+    if (r != RD_OK)
+        return r;
+    if (!phi_prop || !inside)
+        return fail(RD_EINVAL, "phi_prop and inside are required");
+    if (chains->n_chains == 0)
+        return RD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->trace_step0, s));
+    SamplerArgs a = sampler_args(p, chains);
+    a.phi_prop = phi_prop;
+    a.inside = inside;
+    a.theta_prop = nullptr;
+    HIP_TRY(launch_pmh_propose(a, n_prop, s));
+    return RD_OK;
+}
+
+extern "C" int32_t pmh_resample_batch(rd_problem *p, rd_chains *chains, int32_t n_prop,
+                                      const double *phi_prop, const int32_t *inside,
+                                      const double *loglik_prop, void *stream)
+{
+    int32_t r = check_pmh(p, chains, n_prop);
+    if (r != RD_OK)
+        return r;
+    if (!phi_prop || !inside || !loglik_prop)
+        return fail(RD_EINVAL, "phi_prop, inside and loglik_prop are required");
+    hipStream_t s = (hipStream_t)stream;
+    if (chains->n_chains > 0) {
+        HIP_TRY(launch_set_ctr(p->ctr, chains->step, chains->trace_step0, s));
+        SamplerArgs a = sampler_args(p, chains);
+        a.phi_prop = const_cast<double *>(phi_prop);
+        a.inside = const_cast<int *>(inside);
+        a.loglik_prop = loglik_prop;
+        HIP_TRY(launch_pmh_resample(a, n_prop, s));
+    }
+    chains->step += (uint64_t)n_prop;
     return RD_OK;
 }
 

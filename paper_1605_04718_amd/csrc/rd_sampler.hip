@@ -11,7 +11,14 @@
 
 namespace rd {
 
-enum : uint32_t { kPurposeProposal = 0, kPurposeAccept = 1, kPurposeStage1 = 2 };
+enum : uint32_t {
+    kPurposeProposal = 0,
+    kPurposeAccept = 1,
+    kPurposeStage1 = 2,
+    kPurposePmhAux = 6,       // parallel MH: the auxiliary point
+    kPurposePmhProp = 7,      // parallel MH: proposal j from blocks 2j, 2j + 1
+    kPurposePmhResample = 8,  // parallel MH: uniform of draw n from block n
+};
 
 // The four inequalities of eq. (turing) for the activator-depleted kinetics
 // at the homogeneous steady state (a + b, b / (a + b)^2).
@@ -91,6 +98,162 @@ __global__ void k_propose(SamplerArgs a)
         a.theta_prop[4 * c + 3] = d;
     }
     a.inside[c] = in ? 1 : 0;
+}
+
+// Random-walk move of the free coordinates: y = x + s .* z, or x + L z.
+__device__ __forceinline__ void rw_move(const SamplerCfg &cfg, const double *x, const double *z,
+                                        double *y)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        y[i] = x[i];
+        if ((cfg.free_mask >> i) & 1u) {
+            double dz = 0.0;
+            if (cfg.use_chol) {
+                for (int j = 0; j <= i; ++j)
+                    dz = dz + cfg.chol[4 * i + j] * z[j];
+            } else {
+                dz = cfg.step[i] * z[i];
+            }
+            y[i] = y[i] + dz;
+        }
+    }
+}
+
+__device__ __forceinline__ bool in_support(const SamplerCfg &cfg, const double *p, double d)
+{
+    bool in = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (cfg.prior_kind[i] == 0)
+            in = in && (cfg.lo[i] <= p[i]) && (p[i] <= cfg.hi[i]);
+    if (cfg.turing)
+        in = in && turing_space(p[0], p[1], d);
+    return in;
+}
+
+// Parallel Metropolis-Hastings (Sec. 2, Algorithm 2), step 1: item c N + j
+// is proposal j of chain c, drawn around the auxiliary point z = x_c + dz
+// (purpose 6) as z + dz_j (purpose 7, blocks 2j, 2j + 1); Calderhead's
+// construction, for which the matrix A of the algorithm leaves the
+// posterior invariant with a symmetric kernel.
+__global__ void k_pmh_propose(SamplerArgs a, int n_prop)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n * n_prop)
+        return;
+    const int c = t / n_prop, j = t % n_prop;
+    const uint64_t step = a.ctr[0];
+    double z[4], aux[4], p[4];
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, kPurposePmhAux, 0), z[0], z[1]);
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, kPurposePmhAux, 1), z[2], z[3]);
+    rw_move(a.cfg, a.phi + 4 * c, z, aux);
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, kPurposePmhProp, 2 * j), z[0], z[1]);
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, kPurposePmhProp, 2 * j + 1), z[2], z[3]);
+    rw_move(a.cfg, aux, z, p);
+    const double d = exp(p[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        a.phi_prop[4 * t + i] = p[i];
+    if (a.theta_prop) {
+        a.theta_prop[4 * t + 0] = p[0];
+        a.theta_prop[4 * t + 1] = p[1];
+        a.theta_prop[4 * t + 2] = exp(p[2]);
+        a.theta_prop[4 * t + 3] = d;
+    }
+    a.inside[t] = in_support(a.cfg, p, d) ? 1 : 0;
+}
+
+// Steps 3 and 4: the stationary distribution of A over the N + 1 points
+// (x_c and its N proposals).  A is a Metropolis chain with a uniform choice
+// among the other points, so by detailed balance that distribution is the
+// normalised target, p_j = w_j / sum w with log w_j = -Phi_j + log pi0_j
+// (w_j = 0 outside the support).  N draws from it by the running sum in
+// index order, one uniform each (purpose 8, block n), are the chain's next
+// N states (trace rows step .. step + N - 1); the last one is the present
+// state of the next step.  n_accept counts draws other than x_c.
+__global__ void k_pmh_resample(SamplerArgs a, int n_prop)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n)
+        return;
+    const uint64_t step = a.ctr[0];
+    const double *x0 = a.phi + 4 * c;
+    auto logw = [&](int k) -> double {
+        if (k == 0)
+            return -a.loglik[c] - (a.cfg.any_normal ? prior_quad(a.cfg, x0) : 0.0);
+        const int t = c * n_prop + k - 1;
+        if (!a.inside[t])
+            return -__builtin_inf();
+        return -a.loglik_prop[t] -
+               (a.cfg.any_normal ? prior_quad(a.cfg, a.phi_prop + 4 * t) : 0.0);
+    };
+    double mx = -__builtin_inf();
+    for (int k = 0; k <= n_prop; ++k) {
+        const double l = logw(k);
+        if (l > mx)
+            mx = l;
+    }
+    const bool any = mx > -__builtin_inf() && mx == mx;
+    double sum = 0.0;
+    if (any)
+        for (int k = 0; k <= n_prop; ++k) {
+            const double l = logw(k);
+            sum = sum + (l > -__builtin_inf() ? exp(l - mx) : 0.0);
+        }
+    int moved = 0, last = 0, solved = 0;
+    for (int k = 0; k < n_prop; ++k)
+        solved += a.inside[c * n_prop + k] ? 1 : 0;
+    for (int n = 0; n < n_prop; ++n) {
+        int idx = 0;
+        if (any) {
+            const U32x4 w = stream_block(a.seed, (uint32_t)c, step, kPurposePmhResample, n);
+            const double u = unit_open(w.x, w.y);
+            double acc = 0.0;
+            idx = -1;
+            int last_pos = 0;
+            for (int k = 0; k <= n_prop; ++k) {
+                const double l = logw(k);
+                const double pk = l > -__builtin_inf() ? exp(l - mx) / sum : 0.0;
+                if (pk > 0.0)
+                    last_pos = k;
+                acc = acc + pk;
+                if (idx < 0 && u < acc)
+                    idx = k;
+            }
+            if (idx < 0)
+                idx = last_pos;
+        }
+        last = idx;
+        moved += idx != 0;
+        const double *src = idx == 0 ? x0 : a.phi_prop + 4 * (c * n_prop + idx - 1);
+        const uint64_t s = step + (uint64_t)n;
+        if (a.trace && s >= a.ctr[1] && s - a.ctr[1] < (uint64_t)a.trace_rows) {
+            const uint64_t row = s - a.ctr[1];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a.trace[(row * (uint64_t)a.n + c) * 4 + i] = src[i];
+        }
+    }
+    if (a.n_solves)
+        a.n_solves[c] += (uint64_t)solved;
+    if (a.n_accept)
+        a.n_accept[c] += (uint64_t)moved;
+    if (last != 0) {
+        const int t = c * n_prop + last - 1;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a.phi[4 * c + i] = a.phi_prop[4 * t + i];
+        a.loglik[c] = a.loglik_prop[t];
+    }
+}
+
+// Item grid class of a parallel-MH batch: item c N + j has chain c's class.
+__global__ void k_pmh_expand_gid(const int *gid, int n, int n_prop, int *out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n * n_prop)
+        out[t] = gid[t / n_prop];
 }
 
 // Accept iff log U < [Phi(phi) - Phi(phi')] + [log pi(phi') - log pi(phi)],
@@ -233,6 +396,25 @@ static inline dim3 chain_blocks(int n)
 hipError_t launch_propose(const SamplerArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_propose, chain_blocks(a.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pmh_propose(const SamplerArgs &a, int n_prop, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pmh_propose, chain_blocks(a.n * n_prop), dim3(256), 0, s, a, n_prop);
+    return hipGetLastError();
+}
+
+hipError_t launch_pmh_resample(const SamplerArgs &a, int n_prop, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pmh_resample, chain_blocks(a.n), dim3(256), 0, s, a, n_prop);
+    return hipGetLastError();
+}
+
+hipError_t launch_pmh_expand_gid(const int *gid, int n, int n_prop, int *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pmh_expand_gid, chain_blocks(n * n_prop), dim3(256), 0, s, gid, n,
+                       n_prop, out);
     return hipGetLastError();
 }
 

@@ -41,6 +41,12 @@ struct SamplerArgs {
 
 hipError_t launch_propose(const SamplerArgs &a, hipStream_t s);
 hipError_t launch_accept(const SamplerArgs &a, hipStream_t s);
+// Parallel Metropolis-Hastings: a.n chains, n_prop proposals each (items
+// c * n_prop + j of phi_prop, theta_prop, inside and loglik_prop).
+constexpr int kMaxPmhProposals = 256;
+hipError_t launch_pmh_propose(const SamplerArgs &a, int n_prop, hipStream_t s);
+hipError_t launch_pmh_resample(const SamplerArgs &a, int n_prop, hipStream_t s);
+hipError_t launch_pmh_expand_gid(const int *gid, int n, int n_prop, int *out, hipStream_t s);
 hipError_t launch_da_stage1(const SamplerArgs &a, hipStream_t s);
 hipError_t launch_da_stage2(const SamplerArgs &a, hipStream_t s);
 hipError_t launch_set_ctr(uint64_t *ctr, uint64_t step, uint64_t step0, hipStream_t s);

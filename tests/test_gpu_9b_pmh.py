@@ -1,0 +1,148 @@
+"""Parallel Metropolis-Hastings (Sec. 2, Algorithm 2) on the GPU against the
+oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sampler as osamp
+from gpu_common import THETA_TRUE, TAU, make_problem, need_gpu
+from paper_1605_04718_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+LO = np.array([0.0, 0.0, math.log(50.0), math.log(5.0)])
+HI = np.array([1.0, 1.0, math.log(500.0), math.log(50.0)])
+
+
+def chains_at(phi, ll, seed, **kw):
+    import torch
+    from paper_1605_04718_amd.api import ChainState
+    return ChainState.create(torch.tensor(phi, dtype=torch.float64, device="cuda"),
+                             torch.tensor(ll, dtype=torch.float64, device="cuda"), seed=seed, **kw)
+
+
+def _near_tie(p, us, eps):
+    """Some draw's uniform lies within eps of a running-sum boundary."""
+    cs = np.cumsum(p)
+    return any(np.min(np.abs(cs - u)) < eps for u in us)
+
+
+def test_pmh_proposals_match_oracle():
+    import torch
+    need_gpu()
+    C, N = 90, 6
+    step = np.array([0.03, 0.03, 0.1, 0.1])
+    p, _, _ = make_problem(32, 1, lo=LO, hi=HI, step=step, max_batch=C * N)
+    phi = inputs.box_draws(C, LO, HI, seed=18)
+    ch = chains_at(phi, np.zeros(C), seed=202)
+    ch.step = 4321
+    prop, inside = p.pmh_propose(ch, N)
+    torch.cuda.synchronize()
+    prop, inside = prop.cpu().numpy(), inside.cpu().numpy()
+    for c in range(C):
+        want = osamp.pmh_points(phi[c], 202, c, 4321, N, step, 0b1111)[1:]
+        assert np.allclose(prop[c * N:(c + 1) * N], want, rtol=1e-14, atol=1e-14)
+        for j in range(N):
+            assert bool(inside[c * N + j]) == osamp.in_box(want[j], LO, HI)
+    assert 0 < inside.sum() < C * N
+    p.close()
+
+
+def test_pmh_draws_match_oracle_on_an_external_target():
+    """Gaussian toy Phi evaluated on the host for both sides: the GPU's
+    closed-form stationary distribution and the oracle's dense solve give
+    the same draws (draws within 1e-9 of a tie are not compared)."""
+    import torch
+    need_gpu()
+    C, N, S = 64, 8, 4
+    mu = np.array([0.3, 0.6, 5.0, 2.5])
+    sd = np.array([0.05, 0.08, 0.3, 0.2])
+    step = 0.8 * sd
+    lo, hi = np.array([0.0, 0.0, 3.0, 1.0]), np.array([1.0, 1.0, 7.0, 4.0])
+
+    def phi_fn(q):
+        return 0.5 * float((((np.asarray(q) - mu) / sd) ** 2).sum())
+
+    p, _, _ = make_problem(32, 1, lo=lo, hi=hi, step=step, max_batch=C * N)
+    start = np.tile(mu, (C, 1)) + np.outer(np.linspace(-1, 1, C), 0.5 * sd)
+    ll0 = np.array([phi_fn(q) for q in start])
+    ch = chains_at(start, ll0, seed=73, trace_steps=S * N)
+    x, ll = start.copy(), ll0.copy()
+    skipped = compared = moved = 0
+    for s in range(S):
+        prop, inside = p.pmh_propose(ch, N)
+        torch.cuda.synchronize()
+        ph, ins = prop.cpu().numpy(), inside.cpu().numpy()
+        llp = np.array([phi_fn(q) if ins[t] else np.inf for t, q in enumerate(ph)])
+        p.pmh_resample(ch, N, prop, inside, torch.tensor(llp, device="cuda"))
+        torch.cuda.synchronize()
+        trace = ch.trace.cpu().numpy()
+        for c in range(C):
+            d, dl, idx, pts, pll, pw = osamp.pmh_step(x[c], ll[c], 73, c, s * N, N, lo, hi, step,
+                                                      0b1111, phi_fn)
+            us = [oracle.uniform_at(73, c, s * N, osamp.PURPOSE_PMH_RESAMPLE, n) for n in range(N)]
+            if _near_tie(pw, us, 1e-9):
+                skipped += 1
+                x[c] = ch.phi[c].cpu().numpy()  # follow the GPU's chain
+                ll[c] = ch.loglik[c].item()
+                continue
+            assert np.allclose(trace[s * N:(s + 1) * N, c], d, rtol=1e-13, atol=1e-14), (s, c)
+            x[c], ll[c] = d[-1], dl[-1]
+            compared += 1
+            moved += int((idx != 0).sum())
+        assert np.allclose(ch.phi.cpu().numpy(), x, rtol=1e-13, atol=1e-14)
+    assert compared > 0.95 * C * S and moved > 0 and skipped < 0.05 * C * S
+    assert int(ch.n_accept.sum()) >= moved
+    p.close()
+
+
+def test_pmh_step_on_pde_matches_oracle():
+    """pmh_step_batch with the library's fused solve on a 32^2 FP64 problem
+    against the oracle's Algorithm 2 with its own misfits."""
+    need_gpu()
+    n, steps, C, N = 32, 10, 6, 4
+    u0, v0 = inputs.initial_fields(n, 0.1, 0.9)
+    uo, _, _, _ = oracle.forward_solve(THETA_TRUE, u0, v0, TAU, steps, rtol=1e-12)
+    y, sigma = inputs.noisy_data(uo, 0.01)
+    step = np.array([0.003, 0.003, 0.01, 0.01])
+    p, _, _ = make_problem(n, steps, precision=1, y=y, sigma=sigma, u0=u0, v0=v0, lo=LO, hi=HI,
+                           step=step, max_batch=C * N)
+    phi0 = np.tile(inputs.to_sampling(THETA_TRUE)[0], (C, 1))
+    phi0[:, 1] += np.linspace(-0.006, 0.006, C)
+
+    def ll_fn(q):
+        return float(oracle.loglik_batch(inputs.to_natural(q), u0, v0, y, sigma, TAU, steps,
+                                         rtol=1e-12)[0][0])
+
+    ll0 = np.array([ll_fn(q) for q in phi0])
+    ch = chains_at(phi0, ll0, seed=55, trace_steps=N)
+    p.pmh_step(ch, N)
+    trace = ch.trace.cpu().numpy()
+    assert ch.step == N
+    compared = 0
+    for c in range(C):
+        d, dl, idx, pts, pll, pw = osamp.pmh_step(phi0[c], ll0[c], 55, c, 0, N, LO, HI, step,
+                                                  0b1111, ll_fn)
+        us = [oracle.uniform_at(55, c, 0, osamp.PURPOSE_PMH_RESAMPLE, k) for k in range(N)]
+        if _near_tie(pw, us, 1e-6):  # the GPU's misfits differ from the oracle's at ~1e-10
+            continue
+        assert np.allclose(trace[:, c], d, rtol=1e-12, atol=1e-13), c
+        assert ch.loglik[c].item() == pytest.approx(dl[-1], rel=1e-8)
+        compared += 1
+    assert compared >= C - 1
+    assert int(ch.n_solves.sum()) == C * N  # every proposal near theta_true is in the box
+    p.close()
+
+
+def test_pmh_arguments_are_checked():
+    from paper_1605_04718_amd._lib import RDError
+    need_gpu()
+    p, _, _ = make_problem(32, 1, lo=LO, hi=HI, step=(0.01, 0.01, 0.01, 0.01), max_batch=16)
+    ch = chains_at(inputs.box_draws(4, LO, HI, seed=1), np.zeros(4), seed=3)
+    with pytest.raises(RDError):
+        p.pmh_propose(ch, 0)
+    with pytest.raises(RDError):
+        p.pmh_propose(ch, 5)  # 4 x 5 items exceed max_batch = 16
+    p.close()
