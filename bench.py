@@ -227,6 +227,26 @@ def stationary_leg(args, u0, v0, y, sigma, log):
     chd.loglik_sur = lls0.clone()
     da = run_leg(p, chd, DA, 0, S, stream, "stationary da")
     tr_d = chd.trace.cpu().numpy()
+    pmh = None
+    if args.st_pmh > 0:
+        # Algorithm 2 from the same warm start: N proposals per chain and
+        # step (around an auxiliary point), N draws; as many draws per chain
+        # as the other samplers' steps
+        N = args.st_pmh
+        K = max(1, S // N)
+        chp = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER + 10,
+                                trace_steps=K * N)
+        solves0 = int(chp.n_solves.sum())
+        torch.cuda.synchronize()
+        t = time.time()
+        with torch.cuda.stream(stream):
+            for k in range(K):
+                p.pmh_step(chp, N)
+                stream.synchronize()
+                log(f"stationary pmh step {k} ({N} proposals per chain): {time.time() - t:.1f} s")
+        pmh = {"wall": time.time() - t, "solves": int(chp.n_solves.sum()) - solves0,
+               "moved": int(chp.n_accept.sum()), "draws": K * N, "steps": K, "n_prop": N}
+        tr_m = chp.trace.cpu().numpy()
     p.close()
     burn = S // 2
     from paper_1605_04718_amd import stats
@@ -245,21 +265,41 @@ def stationary_leg(args, u0, v0, y, sigma, log):
             row[f"{nm}_diff_in_mcse"] = abs(qp - qd) / sq if sq > 0 else None
         agree[k] = row
     ep, ed = ess_block(tr_p[burn:], plain["wall"]), ess_block(tr_d[burn:], da["wall"])
+    pmh_block = None
+    if pmh is not None:
+        mb = pmh["draws"] // 2
+        sm = stats.summary(tr_m[mb:])
+        for i, k in enumerate(names):
+            se = math.hypot(sp[k]["mcse_mean"], sm[k]["mcse_mean"])
+            agree[k]["mean_pmh"] = sm[k]["mean"]
+            agree[k]["mean_diff_pmh_in_mcse"] = (abs(sp[k]["mean"] - sm[k]["mean"]) / se
+                                                  if se > 0 else None)
+        em = ess_block(tr_m[mb:], pmh["wall"])
+        pmh_block = {"wall_s": pmh["wall"], "n_prop": pmh["n_prop"], "steps": pmh["steps"],
+                     "draws_per_chain": pmh["draws"], "solves": pmh["solves"],
+                     "moved_fraction": pmh["moved"] / (C * pmh["draws"]), **em,
+                     "ess_per_solve": (em["min_bulk_ess"] / pmh["solves"]
+                                       if em["min_bulk_ess"] else None)}
     return {
         "workload": f"{C} chains x {S} steps (second half kept), 128x128, T=2, CG rtol {rtol}, "
                     "correlated random walk with the Laplace covariance x 2.38^2/4, warm start "
                     "from the Laplace approximation at the data-generating parameters",
         "laplace_marginal_sd": msd.tolist(),
         "plain": {"wall_s": plain["wall"], "accept_rate": plain["accepted"] / (C * S),
-                  "solves": plain["solves"], **ep},
+                  "solves": plain["solves"], **ep,
+                  "ess_per_solve": (ep["min_bulk_ess"] / plain["solves"]
+                                    if ep["min_bulk_ess"] else None)},
         "da": {"wall_s": da["wall"], "accept_rate": da["accepted"] / (C * S),
                "stage1_accept_rate": da["accepted1"] / (C * S), "solves": da["solves"],
-               "surrogate_held_out": rep["held_out"], "surrogate_fit_s": fit_s, **ed},
+               "surrogate_held_out": rep["held_out"], "surrogate_fit_s": fit_s, **ed,
+               "ess_per_solve": (ed["min_bulk_ess"] / da["solves"]
+                                 if ed["min_bulk_ess"] else None)},
         "ess_per_sec_speedup": (ed["ess_per_sec"] / ep["ess_per_sec"]
                                 if ed["ess_per_sec"] and ep["ess_per_sec"] else None),
         "da_ess_per_sec_incl_surrogate_fit": (ed["min_bulk_ess"] / (da["wall"] + fit_s)
                                               if ed["min_bulk_ess"] else None),
         "posterior_mean_agreement": agree,
+        "pmh": pmh_block,
     }
 
 
@@ -464,6 +504,8 @@ def main():
     ap.add_argument("--st-rtol", type=float, default=1e-9)
     ap.add_argument("--st-sur-solves", type=int, default=8192)
     ap.add_argument("--st-sur-epochs", type=int, default=60)
+    ap.add_argument("--st-pmh", type=int, default=0, metavar="N",
+                    help="also run Algorithm 2 (N proposals per chain and step) near stationarity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a known-size kernel that scales "
                          "hardware byte counters)")
