@@ -11,6 +11,7 @@ solves) and exposes it through ctypes with numpy arrays.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -155,6 +156,40 @@ def forward_solve(theta, u0, v0, tau, n_steps, growth=0, rate=0.0, rtol=1e-12, m
     st = lib().orc_forward_solve(n, _d(th), int(growth), float(rate), float(tau), int(n_steps),
                                  float(rtol), int(maxit), _d(u0), _d(v0), _d(u), _d(v), _i(it))
     return u, v, it, st
+
+
+ST_NOT_STEADY = 32
+
+
+def time_derivative_norm(u, v, u_next, v_next, tau) -> float:
+    """L2 norm over the unit square of the discrete time derivative of (u, v)
+    (cell-centred quadrature, h = 1/n): sqrt(h^2 sum (du^2 + dv^2)) / tau."""
+    n = np.asarray(u).shape[-1]
+    du = _f64(u_next) - _f64(u)
+    dv = _f64(v_next) - _f64(v)
+    return math.sqrt(float((du * du).sum() + (dv * dv).sum())) / (n * tau)
+
+
+def forward_solve_steady(theta, u0, v0, tau, max_steps, tol, growth=0, rate=0.0, rtol=1e-12,
+                         maxit=None):
+    """Sec. 3.1.2: step until the L2 norm of the discrete time derivative
+    of (u, v) falls below tol (the fields after that step are the result),
+    at most max_steps steps (then status ST_NOT_STEADY).
+
+    Returns (u, v, steps, iters[2], status)."""
+    u, v = _f64(u0).copy(), _f64(v0).copy()
+    its = np.zeros(2, dtype=np.int64)
+    for s in range(max_steps):
+        un, vn, it, st = imex_step(theta, u, v, tau, t_n=s * tau, growth=growth, rate=rate,
+                                   rtol=rtol, maxit=maxit)
+        its += it
+        if st:
+            return un, vn, s + 1, its, st
+        dnorm = time_derivative_norm(u, v, un, vn, tau)
+        u, v = un, vn
+        if dnorm < tol:
+            return u, v, s + 1, its, 0
+    return u, v, max_steps, its, ST_NOT_STEADY
 
 
 def misfit(y, u, sigma) -> float:
