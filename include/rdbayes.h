@@ -64,7 +64,8 @@ enum {
     RD_ST_BREAKDOWN = 2,     /* p.Ap <= 0: the implicit operator lost definiteness */
     RD_ST_NONFINITE = 4,     /* NaN/Inf in a field or reduction */
     RD_ST_OUT_OF_PRIOR = 8,  /* proposal outside the prior box: not solved */
-    RD_ST_BAD_GRID = 16      /* grid_id outside [0, n_grids): not solved */
+    RD_ST_BAD_GRID = 16,     /* grid_id outside [0, n_grids): not solved */
+    RD_ST_NOT_STEADY = 32    /* steady-state stopping: n_steps reached first */
 };
 
 enum { RD_PRECISION_FP32 = 0, RD_PRECISION_FP64 = 1 };
@@ -120,6 +121,12 @@ typedef struct {
     double prior_mean[4];
     double prior_sd[4];            /* > 0 where prior_kind is RD_PRIOR_NORMAL */
     int32_t turing_support;
+    /* Steady-state stopping (Sec. 3.1.2): steady_tol > 0 ends each solve
+     * after the first step whose discrete time derivative of (u, v) has an
+     * L2 norm over the unit square below steady_tol,
+     * sqrt(h^2 sum (du^2 + dv^2)) / dt with h = 1/n; n_steps is then a cap
+     * (reaching it sets RD_ST_NOT_STEADY, Phi = +inf).  0: fixed horizon. */
+    double steady_tol;
 } rd_problem_desc;
 
 enum { RD_PRIOR_UNIFORM = 0, RD_PRIOR_NORMAL = 1 };
@@ -133,6 +140,13 @@ int32_t init_problem(const rd_problem_desc *desc, rd_problem **out);
 
 /* Releases the workspace (synchronises the device first).  NULL is a no-op. */
 int32_t destroy_problem(rd_problem *p);
+
+/* forward_solve_batch plus steps_out (dev int32 [n]): the IMEX steps each
+ * item took (its stopping step with steady-state stopping, else n_steps). */
+int32_t forward_solve_steady_batch(rd_problem *p, int32_t n, const double *theta,
+                                   const int32_t *grid_id, void *u_out, void *v_out,
+                                   int32_t *status, int32_t *cg_iters, int32_t *steps_out,
+                                   void *stream);
 
 /* G(theta) for n parameter vectors (Sec. 2 observation operator): integrate
  * each from the initial fields of its grid class to T.

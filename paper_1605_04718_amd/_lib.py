@@ -33,7 +33,8 @@ class ProblemDesc(ctypes.Structure):
                 ("n_steps", c_i32), ("cg_rtol", c_d), ("cg_maxit", c_i32), ("precision", c_i32),
                 ("free_mask", c_u32), ("lo", c_d * 4), ("hi", c_d * 4), ("step", c_d * 4),
                 ("max_batch", c_i32), ("prop_chol", c_d * 16), ("prior_kind", c_i32 * 4),
-                ("prior_mean", c_d * 4), ("prior_sd", c_d * 4), ("turing_support", c_i32)]
+                ("prior_mean", c_d * 4), ("prior_sd", c_d * 4), ("turing_support", c_i32),
+                ("steady_tol", c_d)]
 
 
 class Chains(ctypes.Structure):
@@ -65,6 +66,8 @@ SYMBOLS = {
     "surrogate_params": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_vp]),
     "rd_autotune": (c_i32, [c_vp, c_vp]),
     "rd_set_tile": (c_i32, [c_vp, c_i32, c_i32]),
+    "forward_solve_steady_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                           c_vp]),
     "rd_set_mixed_threads": (c_i32, [c_vp, c_i32]),
     "rd_solver_timing": (c_i32, [c_vp, c_i32, c_dp, ctypes.POINTER(c_i64), c_i32]),
     "rd_mixed_threads": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),

@@ -53,12 +53,14 @@ class Problem:
                  free_mask=0b1111, lo=(0, 0, 0, 0), hi=(1, 1, 1, 1), step=(0, 0, 0, 0),
                  max_batch=4096, prop_chol=None, prior_kind=(0, 0, 0, 0),
                  prior_mean=(0.0, 0.0, 0.0, 0.0), prior_sd=(1.0, 1.0, 1.0, 1.0),
-                 turing_support=False):
+                 turing_support=False, steady_tol=0.0):
         """prop_chol: optional lower-triangular 4 x 4 factor L of a correlated
         random-walk step (phi' = phi + L z); step is then unused.
         prior_kind[i]: 0 uniform on [lo[i], hi[i]], 1 normal N(prior_mean[i],
         prior_sd[i]^2) in sampling coordinate i (log-normal in gamma, d);
-        turing_support: restrict the support to the Turing space."""
+        turing_support: restrict the support to the Turing space.
+        steady_tol > 0: stop each solve at the first step whose time
+        derivative has an L2 norm below steady_tol (n_steps is the cap)."""
         if isinstance(grids, Grid):
             grids = [grids]
         self.grids = list(grids)
@@ -103,6 +105,7 @@ class Problem:
             d.prior_mean[i] = float(prior_mean[i])
             d.prior_sd[i] = float(prior_sd[i])
         d.turing_support = int(bool(turing_support))
+        d.steady_tol = float(steady_tol)
         if prop_chol is not None:
             L = np.asarray(prop_chol, dtype=np.float64).reshape(4, 4)
             for i in range(4):
@@ -147,6 +150,23 @@ class Problem:
         check(lib().forward_solve_batch(self.h, n, _ptr(theta), _ptr(grid_id), _ptr(u), _ptr(v),
                                         _ptr(st), _ptr(it), _stream(stream)), "forward_solve_batch")
         return u, v, st, it
+
+    def forward_solve_steady(self, theta, grid_id=None, stream=None):
+        """forward_solve plus the IMEX steps each item took: (u, v, status,
+        iters, steps int32 [n])."""
+        n = theta.shape[0]
+        M = max(g.n for g in self.grids)
+        shape = (n, M, M) if len(self.grids) == 1 else (n, M * M)
+        dev = theta.device
+        u = torch.empty(shape, dtype=self.field_dtype, device=dev)
+        v = torch.empty(shape, dtype=self.field_dtype, device=dev)
+        st = torch.empty(n, dtype=torch.int32, device=dev)
+        it = torch.empty((n, 2), dtype=torch.int32, device=dev)
+        steps = torch.empty(n, dtype=torch.int32, device=dev)
+        check(lib().forward_solve_steady_batch(self.h, n, _ptr(theta), _ptr(grid_id), _ptr(u),
+                                               _ptr(v), _ptr(st), _ptr(it), _ptr(steps),
+                                               _stream(stream)), "forward_solve_steady_batch")
+        return u, v, st, it, steps
 
     def log_likelihood(self, theta, grid_id=None, stream=None):
         """Returns (phi float64 [n], status int32 [n], iters int32 [n, 2])."""

@@ -193,7 +193,7 @@ hipError_t record_solve_end(rd_problem *p, hipStream_t s, hipEvent_t start)
 // the autotuner times each class on its own).
 int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid_id,
                       const int *need, double *phi, int *status, int *iters, void *u_out,
-                      void *v_out, hipStream_t s, int cls = 0)
+                      void *v_out, hipStream_t s, int cls = 0, int *steps_out = nullptr)
 {
     if (n == 0)
         return RD_OK;
@@ -225,6 +225,8 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     a.gws_slots = p->gws_slots;
     a.coop = p->coop;
     a.coop_groups = p->coop_groups;
+    a.steady_tt = p->desc.steady_tol > 0.0 ? p->desc.steady_tol * p->desc.dt : 0.0;
+    a.steps_out = steps_out;
     const TileChoice t = p->tile[g];
     // wgs_per_cu was queried when the tile was chosen: no runtime query may
     // run here, since this is also called while a stream is being captured.
@@ -410,6 +412,8 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     }
     if (desc->turing_support != 0 && desc->turing_support != 1)
         return fail(RD_EINVAL, "turing_support must be 0 or 1");
+    if (!(desc->steady_tol >= 0.0) || !std::isfinite(desc->steady_tol))
+        return fail(RD_EINVAL, "steady_tol must be finite and >= 0");
     for (int g = 0; g < desc->n_grids; ++g) {
         const rd_grid_desc &gd = desc->grids[g];
         if (!tile_supported(gd.n, desc->precision, default_cpt(gd.n, desc->precision)))
@@ -601,6 +605,20 @@ extern "C" int32_t forward_solve_batch(rd_problem *p, int32_t n, const double *t
         return fail(RD_EINVAL, "theta and status are required");
     return enqueue_solve(p, n, theta, grid_id, nullptr, nullptr, status, cg_iters, u_out, v_out,
                          (hipStream_t)stream);
+}
+
+extern "C" int32_t forward_solve_steady_batch(rd_problem *p, int32_t n, const double *theta,
+                                              const int32_t *grid_id, void *u_out, void *v_out,
+                                              int32_t *status, int32_t *cg_iters,
+                                              int32_t *steps_out, void *stream)
+{
+    int32_t r = check_batch(p, n);
+    if (r != RD_OK)
+        return r;
+    if (n > 0 && (!status || !theta || !steps_out))
+        return fail(RD_EINVAL, "theta, status and steps_out are required");
+    return enqueue_solve(p, n, theta, grid_id, nullptr, nullptr, status, cg_iters, u_out, v_out,
+                         (hipStream_t)stream, 0, steps_out);
 }
 
 extern "C" int32_t log_likelihood_batch(rd_problem *p, int32_t n, const double *theta,
@@ -1103,6 +1121,7 @@ extern "C" const char *rd_status_string(int32_t s)
     case RD_ST_NONFINITE: return "non-finite value";
     case RD_ST_OUT_OF_PRIOR: return "outside the prior box";
     case RD_ST_BAD_GRID: return "grid id outside [0, n_grids)";
+    case RD_ST_NOT_STEADY: return "no steady state within n_steps";
     default: return "combination of status flags";
     }
 }

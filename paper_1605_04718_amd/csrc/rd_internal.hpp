@@ -10,7 +10,8 @@ enum : int {
     kStBreakdown = 2,
     kStNonfinite = 4,
     kStOutOfPrior = 8,
-    kStBadGrid = 16
+    kStBadGrid = 16,
+    kStNotSteady = 32
 };
 
 // One grid class as the kernels see it (device memory).
@@ -56,6 +57,8 @@ struct SolveArgs {
     void *coop;              // cooperative-solve workspace (per group: partial sums
                              // and edge rows), or null
     int coop_groups;         // groups the workspace holds
+    double steady_tt;        // steady-state stopping: threshold x dt (0: fixed horizon)
+    int *steps_out;          // [n] IMEX steps taken (null: skip)
     int coop_wgs;            // class-ordered batch: nonzero when a cooperative
                              // launch serves the 256^2 items (the mixed launch
                              // then skips them)

@@ -451,8 +451,12 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
 // loads are all issued before the first use: on this architecture stores
 // count in the same counter as loads, so a load placed after the previous
 // cell's store would wait for that store as well, one round trip per cell.
+//
+// acc (optional): adds sum over own cells of d^2 (FP64), the squared size of
+// the step for the steady-state test.
 template <int N, int R, int U, bool kDGlobal, typename Real, class Arr>
-__device__ __forceinline__ void fold(Arr &hi, Arr &d, Real *lo, Real *H, const Geo<N, R> &g)
+__device__ __forceinline__ void fold(Arr &hi, Arr &d, Real *lo, Real *H, const Geo<N, R> &g,
+                                     double *acc = nullptr)
 {
     constexpr bool comp = Compensated<Real>::on;
     const int o = g.off();
@@ -474,6 +478,8 @@ __device__ __forceinline__ void fold(Arr &hi, Arr &d, Real *lo, Real *H, const G
             }
             if (!kDGlobal && H)
                 H[o + k * N] = dk;
+            if (acc)
+                *acc += (double)dk * (double)dk;
         }
         return;
     }
@@ -505,6 +511,8 @@ __device__ __forceinline__ void fold(Arr &hi, Arr &d, Real *lo, Real *H, const G
         }
         if (!kDGlobal && H)
             H[o + k * N] = dd[k];
+        if (acc)
+            *acc += (double)dd[k] * (double)dd[k];
     }
 }
 
@@ -537,10 +545,16 @@ struct SlotLayout {
 // four strip arrays in VGPRs.  Streamed variant: all arrays are global and
 // `stash` is null.  `slot` is the item's global slot (SlotLayout).
 template <int N, int R, int U, int NW, bool kLds, typename Real, class Arr>
+//
+// steady_tt > 0 (Sec. 3.1.2): stop after the first step whose discrete time
+// derivative has an L2 norm over the unit square below the threshold,
+// sqrt(h^2 sum (du^2 + dv^2)) / dt < tol with h = 1/N, i.e. sum (du^2 + dv^2)
+// < (tol dt N)^2 with steady_tt = tol dt; n_steps is then the cap, and an
+// item that reaches it gets kStNotSteady.  `steps` returns the steps taken.
 __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double th[4],
                          const GridDev &gd, double dt, int n_steps, double rtol2, int maxit,
                          Real *P, Real *stash, Real *slot, double *red, const Geo<N, R> &g,
-                         int &itu, int &itv)
+                         int &itu, int &itv, double steady_tt, int &steps)
 {
     using L = SlotLayout<Real>;
     constexpr bool comp = Compensated<Real>::on;
@@ -622,11 +636,23 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
         }
         if (st)
             break;
-        fold<N, R, U, false>(xv, d, lo_v, h_v, g);
-        fold<N, R, U, true>(xu, d, lo_u, h_u, g);
+        steps = s + 1;
+        if (steady_tt > 0.0) {
+            double acc = 0.0;
+            fold<N, R, U, false>(xv, d, lo_v, h_v, g, &acc);
+            fold<N, R, U, true>(xu, d, lo_u, h_u, g, &acc);
+            const double thr = steady_tt * (double)N;
+            if (block_sum<NW>(acc, red + Slots<NW>::misfit) < thr * thr)
+                return st;
+        } else {
+            fold<N, R, U, false>(xv, d, lo_v, h_v, g);
+            fold<N, R, U, true>(xu, d, lo_u, h_u, g);
+        }
         last_u = uniform(itu - itu0);
         last_v = uniform(itv - itv0);
     }
+    if (!st && steady_tt > 0.0)
+        st = kStNotSteady;  // the cap came first
     return st;
 }
 
@@ -653,7 +679,8 @@ __device__ __forceinline__ void load_initial(const GridDev &gd, Arr &xu, Arr &xv
 
 template <int N, int R, typename Real, class Arr>
 __device__ void finish_item(const SolveArgs &a, const GridDev &gd, int c, Arr &xu, Arr &xv, int st,
-                            int itu, int itv, const Real *slot, const Geo<N, R> &g, double *red)
+                            int itu, int itv, const Real *slot, const Geo<N, R> &g, double *red,
+                            int steps)
 {
     using L = SlotLayout<Real>;
     constexpr int NW = (N * N / R) / kWave;
@@ -688,6 +715,8 @@ __device__ void finish_item(const SolveArgs &a, const GridDev &gd, int c, Arr &x
     }
     if (threadIdx.x == 0) {
         a.status[c] = st;
+        if (a.steps_out)
+            a.steps_out[c] = steps;
         if (a.iters) {
             a.iters[2 * c] = itu;
             a.iters[2 * c + 1] = itv;
@@ -733,10 +762,11 @@ __device__ __forceinline__ void solve_item_resident(const SolveArgs &a, int c, c
                           a.theta[4 * c + 3]};
     RegArr<Real, R> xu, xv, r, q, d;
     load_initial<N, R, R>(gd, xu, xv, slot, g);
-    int itu = 0, itv = 0;
+    int itu = 0, itv = 0, steps = 0;
     const int st = integrate<N, R, R, NW, true>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps, a.rtol2,
-                                                a.maxit, P, stash, slot, red, g, itu, itv);
-    finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
+                                                a.maxit, P, stash, slot, red, g, itu, itv,
+                                                a.steady_tt, steps);
+    finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red, steps);
 }
 
 // One item, streamed variant: the strip arrays and p follow the SlotLayout
@@ -757,11 +787,11 @@ __device__ __forceinline__ void solve_item_streamed(const SolveArgs &a, int c, c
     const double th[4] = {a.theta[4 * c], a.theta[4 * c + 1], a.theta[4 * c + 2],
                           a.theta[4 * c + 3]};
     load_initial<N, R, U>(gd, xu, xv, slot, g);
-    int itu = 0, itv = 0;
+    int itu = 0, itv = 0, steps = 0;
     const int st = integrate<N, R, U, NW, false>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps, a.rtol2,
                                                  a.maxit, P, (Real *)nullptr, slot, red, g, itu,
-                                                 itv);
-    finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red);
+                                                 itv, a.steady_tt, steps);
+    finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red, steps);
 }
 
 template <int N, int R, typename Real>
@@ -1396,7 +1426,8 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
 // fold for the member's strip (same arithmetic as fold()).
 template <bool kDGlobal>
 __device__ __forceinline__ void fold_coop(RegArr<float, kCoopR> &hi, RegArr<float, kCoopR> &d,
-                                          float *lo, float *H, const CoopGeo &g)
+                                          float *lo, float *H, const CoopGeo &g,
+                                          double *acc = nullptr)
 {
     const int o = g.off();
     float l[kCoopR], dd[kCoopR];
@@ -1421,6 +1452,8 @@ __device__ __forceinline__ void fold_coop(RegArr<float, kCoopR> &hi, RegArr<floa
         lo[o + k * kCoopN] = lk - (nh - s);
         if (!kDGlobal)
             H[o + k * kCoopN] = dd[k];
+        if (acc)
+            *acc += (double)dd[k] * (double)dd[k];
     }
 }
 
@@ -1456,7 +1489,7 @@ __device__ void solve_item_coop(const SolveArgs &a, int c, const GridDev &gd, fl
     const double n2 = (double)N * (double)N;
     const double decay = gd.decay;
     double rho_m2 = 1.0;
-    int st = 0, itu = 0, itv = 0, last_u = 0, last_v = 0;
+    int st = 0, itu = 0, itv = 0, last_u = 0, last_v = 0, steps = 0;
     LdsArr<float, N> sv{stash + g.sidx(0)};
     for (int s = 0; s < a.n_steps; ++s, rho_m2 = uniform(rho_m2 * decay)) {
         const float cu = uniform((float)(rho_m2 * n2));
@@ -1489,10 +1522,24 @@ __device__ void solve_item_coop(const SolveArgs &a, int c, const GridDev &gd, fl
             xu[k] = sv[k];
         if (st)
             break;
-        fold_coop<false>(xv, d, lo_v, h_v, g);
-        fold_coop<true>(xu, d, lo_u, h_u, g);
+        steps = s + 1;
+        if (a.steady_tt > 0.0) {
+            // steady-state test on the group's sum of squared increments
+            double v1[1] = {0.0};
+            fold_coop<false>(xv, d, lo_v, h_v, g, &v1[0]);
+            fold_coop<true>(xu, d, lo_u, h_u, g, &v1[0]);
+            coop_sum<NW>(v1, red, x);
+            const double thr = a.steady_tt * (double)N;
+            if (v1[0] < thr * thr)
+                break;
+        } else {
+            fold_coop<false>(xv, d, lo_v, h_v, g);
+            fold_coop<true>(xu, d, lo_u, h_u, g);
+        }
         last_u = uniform(itu - itu0);
         last_v = uniform(itv - itv0);
+        if (s + 1 == a.n_steps && a.steady_tt > 0.0)
+            st = kStNotSteady;  // the cap came first
     }
     // outputs: each member writes its rows; misfit summed over the group
     const size_t off = (size_t)c * a.out_stride + (size_t)x.m * strip;
@@ -1524,6 +1571,8 @@ __device__ void solve_item_coop(const SolveArgs &a, int c, const GridDev &gd, fl
     }
     if (threadIdx.x == 0 && x.m == 0) {
         a.status[c] = st;
+        if (a.steps_out)
+            a.steps_out[c] = steps;
         if (a.iters) {
             a.iters[2 * c] = itu;
             a.iters[2 * c + 1] = itv;
