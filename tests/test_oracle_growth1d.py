@@ -1,0 +1,79 @@
+"""Pins of the 1-D growing-domain oracle (Sec. 3.1.2, Example 1), CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import growth1d as g1
+
+
+def test_growth_polynomial_meets_its_end_conditions():
+    T, rho_T = 600.0, 1.8
+    beta = (0.3, -0.2, 0.5)
+    assert g1.rho_poly(beta, rho_T, T, 0.0)[0] == 1.0
+    assert g1.rho_poly(beta, rho_T, T, T)[0] == pytest.approx(rho_T, abs=1e-14)
+    for t in (10.0, 250.0, 590.0):
+        h = 1e-3
+        num = (g1.rho_poly(beta, rho_T, T, t + h)[0] - g1.rho_poly(beta, rho_T, T, t - h)[0]) / (2 * h)
+        assert g1.rho_poly(beta, rho_T, T, t)[1] == pytest.approx(num, rel=1e-8)
+
+
+def test_data_growth_laws():
+    """Both laws start at 1 and end at (nearly) the same size at T = 600, as
+    the text states for the reading with exp(0.6); as printed, exp(0.006)
+    would end the logistic law at 1.006."""
+    assert g1.rho_exp(0.0) == 1.0 and g1.rho_log(0.0) == 1.0
+    assert abs(g1.rho_log(600.0) / g1.rho_exp(600.0) - 1.0) < 3e-3
+    e6 = math.exp(6.0)
+    assert abs(e6 / (1 + (e6 - 1) / math.exp(0.006)) - 1.006) < 1e-3
+    for fn in (g1.rho_exp_pair, g1.rho_log_pair):
+        for t in (5.0, 300.0):
+            h = 1e-3
+            num = (fn(t + h)[0] - fn(t - h)[0]) / (2 * h)
+            assert fn(t)[1] == pytest.approx(num, rel=1e-7)
+
+
+def test_uniform_fields_follow_the_scalar_recursion():
+    """Constant fields have zero Laplacian: each step is the scalar IMEX
+    update with the dilution term rho'/rho (checks reaction and dilution)."""
+    theta = (0.1, 0.9, 1000.0, 10.0)
+    a, b, g, d = theta
+    n, tau, steps, T, rho_T = 20, 1e-4, 50, 600.0, 1.8
+    beta = (0.4, 0.1, 0.2)
+    u, v = np.full(n, 1.02), np.full(n, 0.88)
+    us, vs = 1.02, 0.88
+    for s in range(steps):
+        rho, drho = g1.rho_poly(beta, rho_T, T, s * tau)
+        u, v = g1.imex_step(theta, u, v, tau, rho, drho)
+        dil = drho / rho
+        us, vs = ((us / tau + g * a) / (1 / tau + dil + g * (1 - us * vs)),
+                  (vs / tau + g * b) / (1 / tau + dil + g * us * us))
+    assert np.abs(u - us).max() < 1e-13 and np.abs(v - vs).max() < 1e-13
+
+
+def test_pure_diffusion_mode_on_a_growing_domain():
+    """gamma = 0: a cosine mode k of amplitude A evolves as
+    A' = (A / tau) / (1/tau + rho'/rho + lam / rho^2), lam = 4 n^2 sin^2(k pi / 2n)
+    (checks the 3-point stencil, the mirror boundary and the rho^-2 scale)."""
+    theta = (0.0, 0.0, 0.0, 3.0)
+    n, tau, steps, T, rho_T = 32, 1e-3, 40, 1.0, 1.5
+    beta = (0.2, 0.1, 0.05)
+    x = (np.arange(n) + 0.5) / n
+    k = 3
+    phi = np.cos(k * math.pi * x)
+    lam = 4.0 * n * n * math.sin(k * math.pi / (2 * n)) ** 2
+    u, v = 0.3 * phi, -0.2 * phi
+    Au, Av = 0.3, -0.2
+    for s in range(steps):
+        rho, drho = g1.rho_poly(beta, rho_T, T, s * tau)
+        u, v = g1.imex_step(theta, u, v, tau, rho, drho)
+        Au = (Au / tau) / (1 / tau + drho / rho + lam / rho ** 2)
+        Av = (Av / tau) / (1 / tau + drho / rho + 3.0 * lam / rho ** 2)
+    assert np.abs(u - Au * phi).max() < 1e-13 and np.abs(v - Av * phi).max() < 1e-13
+
+
+def test_initial_fields_printed_form():
+    u0, v0 = g1.initial_fields(100)
+    x = (np.arange(100) + 0.5) / 100
+    assert u0[37] == pytest.approx(1 + 0.005 * sum(math.sin(k * math.pi * x[37]) for k in range(1, 10)))
+    assert np.allclose(v0 - u0, -0.1)
