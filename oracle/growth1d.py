@@ -113,3 +113,27 @@ def misfit(y, u, sigma):
     """Phi = 1/2 sigma^-2 sum (y - u)^2 (Gaussian noise on u)."""
     r = np.asarray(y, dtype=np.float64) - np.asarray(u, dtype=np.float64)
     return 0.5 * float((r * r).sum()) / (sigma * sigma)
+
+
+def growth_positive(beta, rho_T, tau, n_steps):
+    """rho(t_k) > 0 at every step time t_k = k tau, k < n_steps (the growth
+    function must stay positive; the step uses rho at t_k only)."""
+    T = n_steps * tau
+    return all(rho_poly(beta, rho_T, T, k * tau)[0] > 0.0 for k in range(n_steps))
+
+
+def loglik_beta(theta, beta, rho_T, u0, v0, tau, n_steps, y, sigma, obs=1):
+    """Phi(beta) with Gaussian noise on the observed rows of y = [y_u, y_v]
+    (obs bit 0: u, bit 1: v); +inf where rho is not positive."""
+    if not growth_positive(beta, rho_T, tau, n_steps):
+        return math.inf
+    u, v = forward_beta(theta, beta, rho_T, u0, v0, tau, n_steps)
+    y = np.asarray(y, dtype=np.float64).reshape(2, -1)
+    parts_y, parts_g = [], []
+    if obs & 1:
+        parts_y.append(y[0])
+        parts_g.append(u)
+    if obs & 2:
+        parts_y.append(y[1])
+        parts_g.append(v)
+    return misfit(np.concatenate(parts_y), np.concatenate(parts_g), sigma)

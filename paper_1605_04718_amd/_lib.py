@@ -1,4 +1,5 @@
-"""ctypes binding of librdbayes.so (the C ABI declared in include/rdbayes.h).
+"""ctypes binding of librdbayes.so (the C ABI declared in include/rdbayes.h and
+include/rdbayes_growth1d.h).
 
 Argument marshalling only: device arrays are torch tensors on the current
 HIP device (passed as raw pointers), host arrays are numpy arrays.  Every
@@ -37,6 +38,17 @@ class ProblemDesc(ctypes.Structure):
                 ("steady_tol", c_d)]
 
 
+class G1dDesc(ctypes.Structure):
+    _fields_ = [("n", c_i32), ("n_steps", c_i32), ("tau", c_d), ("theta", c_d * 4),
+                ("law", c_i32), ("rho_T", c_d), ("u0", c_dp), ("v0", c_dp), ("y", c_dp),
+                ("obs", c_i32), ("sigma", c_d), ("max_batch", c_i32), ("lo", c_d * 3),
+                ("hi", c_d * 3), ("step", c_d * 3), ("prior_kind", c_i32 * 3),
+                ("prior_mean", c_d * 3), ("prior_sd", c_d * 3)]
+
+
+G1D_LAW_POLY, G1D_LAW_EXP, G1D_LAW_LOGISTIC = 0, 1, 2
+
+
 class Chains(ctypes.Structure):
     _fields_ = [("n_chains", c_i32), ("phi", c_vp), ("loglik", c_vp), ("loglik_sur", c_vp),
                 ("grid_id", c_vp), ("n_accept", c_vp), ("n_accept1", c_vp), ("n_solves", c_vp),
@@ -72,6 +84,11 @@ SYMBOLS = {
     "rd_solver_timing": (c_i32, [c_vp, c_i32, c_dp, ctypes.POINTER(c_i64), c_i32]),
     "rd_mixed_threads": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),
     "surrogate_set_input_box": (c_i32, [c_vp, c_dp, c_dp]),
+    "g1d_init": (c_i32, [ctypes.POINTER(G1dDesc), ctypes.POINTER(c_vp)]),
+    "g1d_destroy": (c_i32, [c_vp]),
+    "g1d_forward_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "g1d_log_likelihood_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "g1d_mcmc_step_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_i32, c_vp]),
     "rd_status_string": (ctypes.c_char_p, [c_i32]),
     "rd_last_error": (ctypes.c_char_p, []),
 }

@@ -324,6 +324,77 @@ class Problem:
         return ms.value, n.value
 
 
+class Growth1D:
+    """Owns a g1d_problem handle: the one-dimensional growing domain of
+    Example 1 (g1d_init / g1d_destroy).  Host arrays are float64 numpy
+    arrays; y is [2, n] (rows u, v) or None."""
+
+    POLY, EXP, LOGISTIC = _lib.G1D_LAW_POLY, _lib.G1D_LAW_EXP, _lib.G1D_LAW_LOGISTIC
+
+    def __init__(self, n, n_steps, tau, theta, u0, v0, *, law=0, rho_T=1.0, y=None, obs=1,
+                 sigma=1.0, max_batch=1024, lo=(-10.0,) * 3, hi=(10.0,) * 3, step=(0.0,) * 3,
+                 prior_kind=(0, 0, 0), prior_mean=(0.0,) * 3, prior_sd=(1.0,) * 3):
+        self._keep = [np.ascontiguousarray(u0, dtype=np.float64),
+                      np.ascontiguousarray(v0, dtype=np.float64)]
+        d = _lib.G1dDesc()
+        d.n, d.n_steps, d.tau, d.law, d.rho_T = n, n_steps, tau, law, rho_T
+        d.theta[:] = [float(x) for x in theta]
+        d.u0 = self._keep[0].ctypes.data_as(_lib.c_dp)
+        d.v0 = self._keep[1].ctypes.data_as(_lib.c_dp)
+        if y is not None:
+            self._keep.append(np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(2, n)))
+            d.y = self._keep[-1].ctypes.data_as(_lib.c_dp)
+        d.obs, d.sigma, d.max_batch = obs, sigma, max_batch
+        d.lo[:], d.hi[:], d.step[:] = ([float(x) for x in lo], [float(x) for x in hi],
+                                       [float(x) for x in step])
+        d.prior_kind[:] = [int(x) for x in prior_kind]
+        d.prior_mean[:] = [float(x) for x in prior_mean]
+        d.prior_sd[:] = [float(x) for x in prior_sd]
+        h = ctypes.c_void_p()
+        check(lib().g1d_init(ctypes.byref(d), ctypes.byref(h)), "g1d_init")
+        self.h, self.n, self.law = h, n, law
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().g1d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, beta=None, m=None, stream=None):
+        """beta: HIP float64 [m, 3] (polynomial law) or None with m items of
+        a data law.  Returns (u, v, status) with u, v float64 [m, n]."""
+        m = beta.shape[0] if beta is not None else (m or 1)
+        dev = beta.device if beta is not None else torch.device("cuda")
+        u = torch.empty((m, self.n), dtype=torch.float64, device=dev)
+        v = torch.empty((m, self.n), dtype=torch.float64, device=dev)
+        st = torch.empty(m, dtype=torch.int32, device=dev)
+        check(lib().g1d_forward_batch(self.h, m, _ptr(beta), _ptr(u), _ptr(v), _ptr(st),
+                                      _stream(stream)), "g1d_forward_batch")
+        return u, v, st
+
+    def log_likelihood(self, beta, stream=None):
+        """Returns (phi float64 [m], status int32 [m])."""
+        m = beta.shape[0]
+        phi = torch.empty(m, dtype=torch.float64, device=beta.device)
+        st = torch.empty(m, dtype=torch.int32, device=beta.device)
+        check(lib().g1d_log_likelihood_batch(self.h, m, _ptr(beta), _ptr(phi), _ptr(st),
+                                             _stream(stream)), "g1d_log_likelihood_batch")
+        return phi, st
+
+    def mcmc_step(self, chains: "ChainState", n_steps=1, stream=None):
+        """Metropolis steps over beta; chains.phi is [C, 4] with beta in the
+        first three columns."""
+        c = chains.struct()
+        check(lib().g1d_mcmc_step_batch(self.h, ctypes.byref(c), n_steps, _stream(stream)),
+              "g1d_mcmc_step_batch")
+        chains.step = int(c.step)
+
+
 @dataclass
 class ChainState:
     """Device state of a batch of chains (the rd_chains struct's arrays)."""

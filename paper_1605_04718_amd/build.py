@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librdbayes.so")
-SOURCES = ["rd_solver.hip", "rd_sampler.hip", "rd_mlp.hip", "rd_capi.hip"]
+SOURCES = ["rd_solver.hip", "rd_sampler.hip", "rd_mlp.hip", "rd_capi.hip", "rd_growth1d.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -33,6 +33,18 @@ int32_t fail(int32_t code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+// Error text for the entry points of the other translation units (not part
+// of the exported interface).
+extern "C" __attribute__((visibility("hidden"))) int32_t rd_set_error(int32_t code, const char *msg)
+{
+    snprintf(g_err, sizeof g_err, "%s", msg);
+    return code;
+}
+
+namespace {
+
 #define HIP_TRY(expr)                                                                  \
     do {                                                                               \
         hipError_t e_ = (expr);                                                        \

@@ -11,6 +11,8 @@ them with the shapes and value distributions of its workloads):
   the kinetics (Sec. 3.1.1, eq. (ic_gturing)) with independent relative
   uniform perturbations of +-rel per cell (Sec. 3.1.2 fixes one known initial
   condition for all proposals);
+* one-dimensional example: the printed initial condition of eq. (ic_gturing)
+  (no random numbers);
 * data: y = u(T; theta_true) + eta, eta ~ N(0, s^2) with s a fraction of the
   range (max - min) of the noise-free field (Sec. 3.1.1, Sec. 3.1.2);
 * parameter draws: uniform on a box in sampling coordinates.
@@ -41,6 +43,17 @@ def initial_fields(n: int, a: float, b: float, rel: float = 0.01, seed: int = SE
     xu = rng.uniform(-1.0, 1.0, size=(n, n))
     xv = rng.uniform(-1.0, 1.0, size=(n, n))
     return us * (1.0 + rel * xu), vs * (1.0 + rel * xv)
+
+
+def initial_fields_1d(n: int):
+    """u0, v0 [n] float64 of eq. (ic_gturing) on the cell centres (i + 1/2)/n
+    of the unit interval: 1 and 0.9 plus 0.005 sum_{k=1..9} sin(k pi x)
+    (the one-dimensional example's fixed initial condition)."""
+    x = (np.arange(n) + 0.5) / n
+    s = np.zeros(n)
+    for k in range(1, 10):
+        s += np.sin(k * np.pi * x)
+    return 1.0 + 0.005 * s, 0.9 + 0.005 * s
 
 
 def standard_normal_field(shape, seed: int = SEED_DATA_NOISE) -> np.ndarray:

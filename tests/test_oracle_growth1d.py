@@ -77,3 +77,26 @@ def test_initial_fields_printed_form():
     x = (np.arange(100) + 0.5) / 100
     assert u0[37] == pytest.approx(1 + 0.005 * sum(math.sin(k * math.pi * x[37]) for k in range(1, 10)))
     assert np.allclose(v0 - u0, -0.1)
+
+
+def test_non_positive_growth_is_outside_the_support():
+    """beta = (-5, 0, 0) with rho(T) = 1.8: rho(T/2) = 1 - 2.5 + 5.8/16 < 0."""
+    assert g1.rho_poly((-5.0, 0.0, 0.0), 1.8, 1.0, 0.5)[0] < 0
+    assert not g1.growth_positive((-5.0, 0.0, 0.0), 1.8, 0.01, 100)
+    assert g1.growth_positive((0.8, 0.0, 0.0), 1.8, 0.01, 100)
+    n = 8
+    u0, v0 = g1.initial_fields(n)
+    y = np.stack([u0, v0])
+    assert g1.loglik_beta((0.1, 0.9, 1000.0, 10.0), (-5.0, 0.0, 0.0), 1.8, u0, v0, 0.01, 100,
+                          y, 0.1) == math.inf
+
+
+def test_loglik_zero_steps_is_the_misfit_of_the_initial_fields():
+    n = 16
+    u0, v0 = g1.initial_fields(n)
+    y = np.stack([u0 + 0.1, v0 - 0.2])
+    th = (0.1, 0.9, 1000.0, 10.0)
+    assert g1.loglik_beta(th, (0.1, 0.2, 0.3), 1.8, u0, v0, 1e-4, 0, y, 0.5, obs=1) == \
+        pytest.approx(0.5 * n * 0.01 / 0.25, rel=1e-14)
+    assert g1.loglik_beta(th, (0.1, 0.2, 0.3), 1.8, u0, v0, 1e-4, 0, y, 0.5, obs=3) == \
+        pytest.approx(0.5 * n * 0.05 / 0.25, rel=1e-14)
