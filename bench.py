@@ -54,6 +54,7 @@ CG_MAXIT = 400
 # linearly with n, so its cap is four times the 128^2 one.
 CG_MAXIT_MIXED = 1600
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed); FLOP/s
+PEAK_FP64 = 78.6e12    # MI355X vector FP64; FLOP/s
 # Algorithmic FP operations of the fused solve (per cell, per species; a
 # fused multiply-add counts 2):
 #   one CG iteration: q = A p (5-point differences 7, c t + sigma p 3), the
@@ -473,6 +474,59 @@ def precision_256_leg(args, log):
     }
 
 
+def growth1d_leg(args, log):
+    """Example 1's one-dimensional growing domain: n = 100 cells, tau = 1e-4,
+    the fused float64 solve + misfit of g1d_log_likelihood_batch for
+    `--g1d-items` prior draws of the three growth coefficients over
+    `--g1d-steps` IMEX steps (the paper's horizon T = 600 is 6e6 steps; the
+    timed horizon is shorter and the full-horizon time is extrapolated).
+    Data: the exponential-growth solution of the same horizon plus 5 %
+    noise.  FLOPs are the kernel's issued float64 operations (a division
+    counted as one): per padded row and reduction level 14, per row and
+    step 13 more for assembly and the final division; 128 rows x 2 systems,
+    7 levels at n = 100."""
+    import torch
+    from paper_1605_04718_amd import inputs
+    from paper_1605_04718_amd.api import Growth1D
+    n, tau, steps, m = 100, 1e-4, args.g1d_steps, args.g1d_items
+    theta = (0.1, 0.9, 1000.0, 10.0)
+    u0, v0 = inputs.initial_fields_1d(n)
+    gdata = Growth1D(n, steps, tau, theta, u0, v0, law=Growth1D.EXP, max_batch=1)
+    ud, vd, _ = gdata.forward(None, m=1)
+    gdata.close()
+    y, sigma = inputs.noisy_data(np.stack([ud[0].cpu().numpy(), vd[0].cpu().numpy()]), 0.05,
+                                 seed=inputs.SEED_DATA_NOISE)
+    rho_T = math.exp(0.001 * steps * tau)
+    g = Growth1D(n, steps, tau, theta, u0, v0, rho_T=rho_T, y=y, obs=3, sigma=sigma,
+                 max_batch=m)
+    beta = torch.tensor(inputs.box_draws(m, (-0.2, -0.2, -0.2), (0.4, 0.2, 0.2),
+                                         seed=inputs.SEED_DATASET), device="cuda")
+    phi, st = g.log_likelihood(beta[:64].contiguous())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    phi, st = g.log_likelihood(beta)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    g.close()
+    levels = math.ceil(math.log2(n))
+    flops = m * steps * 2 * 128 * (14 * levels + 13)
+    achieved = flops / (ms * 1e-3)
+    full_steps = int(round(600 / tau))
+    log(f"growth1d: {m} items x {steps} steps in {ms:.1f} ms")
+    return {
+        "workload": f"Example 1, n={n}, tau={tau}, {m} items x {steps} steps (fused solve + misfit)",
+        "ms": ms, "item_steps_per_s": m * steps / (ms * 1e-3),
+        "cell_steps_per_s": m * steps * n / (ms * 1e-3),
+        "solved": int((st == 0).sum().item()),
+        "full_horizon_seconds_per_batch": ms * 1e-3 * full_steps / steps,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "kernel": "k_g1d_solve", "flops_per_launch": flops},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -504,6 +558,12 @@ def main():
     ap.add_argument("--st-rtol", type=float, default=1e-9)
     ap.add_argument("--st-sur-solves", type=int, default=8192)
     ap.add_argument("--st-sur-epochs", type=int, default=60)
+    ap.add_argument("--growth1d", action="store_true",
+                    help="also time Example 1's 1-D growing-domain likelihood")
+    ap.add_argument("--growth1d-only", action="store_true",
+                    help="run only the 1-D leg and print its JSON object")
+    ap.add_argument("--g1d-items", type=int, default=4096)
+    ap.add_argument("--g1d-steps", type=int, default=20000)
     ap.add_argument("--st-pmh", type=int, default=0, metavar="N",
                     help="also run Algorithm 2 (N proposals per chain and step) near stationarity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -522,6 +582,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
+    if args.growth1d_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"growth1d": growth1d_leg(args, log)}), flush=True)
+        return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
@@ -655,6 +719,8 @@ def main():
         line["precision_256"] = precision_256_leg(args, log)
     if args.stationary:
         line["stationary"] = stationary_leg(args, u0, v0, y, sigma, log)
+    if args.growth1d:
+        line["growth1d"] = growth1d_leg(args, log)
 
     if not args.no_cpu_baseline:
         threads = os.cpu_count() or 1
