@@ -481,10 +481,10 @@ def growth1d_leg(args, log):
     `--g1d-steps` IMEX steps (the paper's horizon T = 600 is 6e6 steps; the
     timed horizon is shorter and the full-horizon time is extrapolated).
     Data: the exponential-growth solution of the same horizon plus 5 %
-    noise.  FLOPs are the kernel's issued float64 operations (a division
+    noise.  FLOPs are the kernel's issued float64 operations (a reciprocal
     counted as one): per padded row and reduction level 14, per row and
-    step 13 more for assembly and the final division; 128 rows x 2 systems,
-    7 levels at n = 100."""
+    step 13 more for assembly and the final solve; 128 rows x 2 systems,
+    6 exchange levels at n = 100 (the seventh is a lane-local 2 x 2 solve)."""
     import torch
     from paper_1605_04718_amd import inputs
     from paper_1605_04718_amd.api import Growth1D
@@ -510,7 +510,7 @@ def growth1d_leg(args, log):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     g.close()
-    levels = math.ceil(math.log2(n))
+    levels = 6 if n > 64 else math.ceil(math.log2(n))
     flops = m * steps * 2 * 128 * (14 * levels + 13)
     achieved = flops / (ms * 1e-3)
     full_steps = int(round(600 / tau))

@@ -7,10 +7,13 @@
 // identity rows (a = c = 0, b = 1, d = 0) that no real row couples to.
 // Parallel cyclic reduction: at stride s every row eliminates its couplings
 // to rows i - s and i + s with those rows' equations, which leaves
-// couplings at stride 2s; after ceil(log2 n) levels each row stands alone
-// and x_i = d_i / b_i.  Every row publishes (a/b, c/b, d/b) once per level
-// (one division per row and level) in LDS, laid out [system][component][row]
-// so that a wave's accesses are consecutive.  The fields stay in registers
+// couplings at stride 2s.  For n <= 64 the levels run until each row stands
+// alone (x_i = d_i / b_i); for n > 64 they stop after stride 32, where row i
+// couples only to i +- 64, so rows L and L + 64 form a 2 x 2 system inside
+// lane L and the last level needs no exchange.  Every row publishes
+// (a/b, c/b, d/b) once per level (one reciprocal per row and level) in LDS,
+// laid out [system][component][row] so that a wave's accesses are
+// consecutive.  The fields stay in registers
 // for the whole horizon; only the data and the results touch HBM.
 #include <math.h>
 #include <stdarg.h>
@@ -68,6 +71,19 @@ struct Row {
     double A, B, C, D;
 };
 
+// 1/x from the hardware estimate refined by two Newton steps (e = 1 - x r,
+// r <- r + r e); each step squares the relative error, so the result is
+// within an ulp or two for the positive, well-scaled pivots of these
+// diagonally dominant systems.
+__device__ inline double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // One reduction level at stride s for the four rows a lane owns.
 // P[sys][comp][row] holds (A/B, C/B, D/B) of every row of the level.
 __device__ inline void pcr_level(Row (&r)[2][2], double (*P)[3][kRows], int lane, int s)
@@ -77,7 +93,7 @@ __device__ inline void pcr_level(Row (&r)[2][2], double (*P)[3][kRows], int lane
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int i = lane + 64 * j;
-            const double rb = 1.0 / r[sys][j].B;
+            const double rb = recip(r[sys][j].B);
             P[sys][0][i] = r[sys][j].A * rb;
             P[sys][1][i] = r[sys][j].C * rb;
             P[sys][2][i] = r[sys][j].D * rb;
@@ -178,12 +194,30 @@ __global__ __launch_bounds__(64) void k_g1d_solve(Args a)
                 r[1][j] = Row{0.0, 1.0, 0.0, 0.0};
             }
         }
-        for (int s = 1; s < n; s <<= 1)
+        const int s_end = n > 64 ? 64 : n;
+        for (int s = 1; s < s_end; s <<= 1)
             pcr_level(r, P, lane, s);
+        if (n > 64) {
+            // rows p = lane and q = lane + 64: B_p x_p + C_p x_q = D_p,
+            // A_q x_p + B_q x_q = D_q (the outward couplings are zero)
+            double x[2][2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            u[j] = r[0][j].D / r[0][j].B;
-            v[j] = r[1][j].D / r[1][j].B;
+            for (int sys = 0; sys < 2; ++sys) {
+                const Row &p = r[sys][0], &q = r[sys][1];
+                const double inv = recip(p.B * q.B - p.C * q.A);
+                x[sys][0] = (p.D * q.B - p.C * q.D) * inv;
+                x[sys][1] = (p.B * q.D - q.A * p.D) * inv;
+            }
+            u[0] = x[0][0];
+            u[1] = x[0][1];
+            v[0] = x[1][0];
+            v[1] = x[1][1];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                u[j] = r[0][j].D * recip(r[0][j].B);
+                v[j] = r[1][j].D * recip(r[1][j].B);
+            }
         }
     }
     double acc = 0.0;
