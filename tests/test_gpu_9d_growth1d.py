@@ -168,3 +168,28 @@ def test_arguments_are_checked():
     with pytest.raises(RDError):
         g.forward(torch.zeros((5, 3), dtype=torch.float64, device="cuda"))  # > max_batch
     g.close()
+
+
+def test_bench_launch_sampled_items_match_oracle():
+    """The launch the 1-D bench leg times (4096 growth-coefficient draws,
+    n = 100, 20 000 steps, data from exponential growth with 5 % noise):
+    misfits of sampled items against the oracle's."""
+    import torch
+    need_gpu()
+    n, steps, m = 100, 20000, 4096
+    u0, v0 = inputs.initial_fields_1d(n)
+    ud, vd = og.forward(THETA1, u0, v0, TAU, steps, og.rho_exp_pair)
+    y, sigma = inputs.noisy_data(np.stack([ud, vd]), 0.05, seed=inputs.SEED_DATA_NOISE)
+    rho_T = math.exp(0.001 * steps * TAU)
+    from paper_1605_04718_amd.api import Growth1D
+    g = Growth1D(n, steps, TAU, THETA1, u0, v0, rho_T=rho_T, y=y, obs=3, sigma=sigma,
+                 max_batch=m)
+    B = inputs.box_draws(m, (-0.2, -0.2, -0.2), (0.4, 0.2, 0.2), seed=inputs.SEED_DATASET)
+    phi, st = g.log_likelihood(torch.tensor(B, device="cuda"))
+    torch.cuda.synchronize()
+    phi, st = phi.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0) and np.all(np.isfinite(phi))
+    for k in (0, 1234, m - 1):
+        want = og.loglik_beta(THETA1, B[k], rho_T, u0, v0, TAU, steps, y, sigma, obs=3)
+        assert phi[k] == pytest.approx(want, rel=1e-9), k
+    g.close()
