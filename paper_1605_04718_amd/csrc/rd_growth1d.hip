@@ -388,10 +388,12 @@ extern "C" int32_t g1d_init(const g1d_desc *d, g1d_problem **out)
         if (!(d->step[i] >= 0.0))
             return fail(RD_EINVAL, "step[%d] must be >= 0", i);
     }
+    int device = 0;
+    G1D_TRY(hipGetDevice(&device));
     g1d_problem *p = new g1d_problem;
     p->desc = *d;
     p->desc.u0 = p->desc.v0 = p->desc.y = nullptr;  // host arrays are read during the call only
-    G1D_TRY(hipGetDevice(&p->device));
+    p->device = device;
     const size_t n = (size_t)d->n, mb = (size_t)d->max_batch;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc(&p->u0, n * sizeof(double));
