@@ -6,11 +6,14 @@
 // output in per-pixel standardised units.  Weights are [out][in] row-major.
 //
 // GEMM kernel: C[M][N] = sum_k A(m, k) B(k, n) on 64 x 64 tiles, K in steps
-// of 32, 256 threads = 4 waves, each wave a 32 x 32 quarter made of 2 x 2
-// v_mfma_f32_16x16x32_bf16 blocks.  Operands are staged through LDS in
-// (row, k) order with k contiguous, so each lane fetches its 8 k-values with
-// one 16-byte LDS read.  Layouts of A and B in global memory are template
-// parameters (forward: H W^T; weight gradient: dZ^T H; input gradient: dZ W).
+// of BK (128 when K allows it, else 32), 256 threads = 4 waves, each wave a
+// 32 x 32 quarter made of 2 x 2 v_mfma_f32_16x16x32_bf16 blocks.  Operands
+// are staged through LDS in (row, k) order with k contiguous, so each lane
+// fetches its 8 k-values with one 16-byte LDS read.  The next K-step's tiles
+// are loaded into registers while the current one is multiplied, so a step
+// waits for global memory once per BK values of k, not once per 32.  Layouts
+// of A and B in global memory are template parameters (forward: H W^T;
+// weight gradient: dZ^T H; input gradient: dZ W).
 // Epilogues fuse bias, GELU and GELU' so that every activation is written
 // once.
 #include <math.h>
@@ -29,7 +32,7 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;
+constexpr int kBM = 64, kBN = 64, kBK = 32, kBKWide = 128, kLdsPad = 8;
 
 __device__ __forceinline__ float gelu_f(float z)
 {
@@ -57,11 +60,14 @@ struct GemmArgs {
 
 // A_KM: A stored [K][M] (A(m,k) = A[k*lda + m]); else [M][K].
 // B_KN: B stored [K][N] (B(k,n) = B[k*ldb + n]); else [N][K].
-template <bool A_KM, bool B_KN, int EPI>
+// Each K-step moves a 64 x BK tile of A and of B: BK / 32 chunks of 8
+// values per thread and operand.
+template <bool A_KM, bool B_KN, int EPI, int BK>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
-    __shared__ __attribute__((aligned(16))) bf16 As[kBM][kBK + kLdsPad];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[kBN][kBK + kLdsPad];
+    constexpr int kChunks = BK / 32;  // 16-byte global loads per thread and operand
+    __shared__ __attribute__((aligned(16))) bf16 As[kBM][BK + kLdsPad];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[kBN][BK + kLdsPad];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -73,44 +79,67 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
         for (int j = 0; j < 2; ++j)
             acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
-        __syncthreads();
-        // A tile: 64 rows (m) x 32 k
-        if (!A_KM) {
-            const int m = t >> 2, kc = (t & 3) * 8;
-            *(bf16x8 *)&As[m][kc] = *(const bf16x8 *)&g.A[(size_t)(m0 + m) * g.lda + k0 + kc];
-        } else {
-            const int k = t >> 3, mc = (t & 7) * 8;
-            const bf16x8 v = *(const bf16x8 *)&g.A[(size_t)(k0 + k) * g.lda + m0 + mc];
+    // chunk c of thread t: [row][k] layout, 64 rows of BK / 8 chunks; or
+    // [k][row] layout, BK k-rows of 8 chunks.
+    auto load = [&](const bf16 *X, int ld, int r0, bool km, int k0, bf16x8 (&v)[kChunks]) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                As[mc + i][k] = v[i];
+        for (int c = 0; c < kChunks; ++c) {
+            const int idx = t + 256 * c;
+            if (!km) {
+                const int row = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
+                v[c] = *(const bf16x8 *)&X[(size_t)(r0 + row) * ld + k0 + kc];
+            } else {
+                const int k = idx >> 3, rc = (idx & 7) * 8;
+                v[c] = *(const bf16x8 *)&X[(size_t)(k0 + k) * ld + r0 + rc];
+            }
         }
-        if (!B_KN) {
-            const int n = t >> 2, kc = (t & 3) * 8;
-            *(bf16x8 *)&Bs[n][kc] = *(const bf16x8 *)&g.B[(size_t)(n0 + n) * g.ldb + k0 + kc];
-        } else {
-            const int k = t >> 3, nc = (t & 7) * 8;
-            const bf16x8 v = *(const bf16x8 *)&g.B[(size_t)(k0 + k) * g.ldb + n0 + nc];
+    };
+    auto stage = [&](bf16 (*S)[BK + kLdsPad], bool km, const bf16x8 (&v)[kChunks]) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                Bs[nc + i][k] = v[i];
+        for (int c = 0; c < kChunks; ++c) {
+            const int idx = t + 256 * c;
+            if (!km) {
+                const int row = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
+                *(bf16x8 *)&S[row][kc] = v[c];
+            } else {
+                const int k = idx >> 3, rc = (idx & 7) * 8;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    S[rc + i][k] = v[c][i];
+            }
         }
+    };
+    bf16x8 va[kChunks], vb[kChunks];
+    load(g.A, g.lda, m0, A_KM, 0, va);
+    load(g.B, g.ldb, n0, B_KN, 0, vb);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        __syncthreads();  // the previous step's LDS reads are done
+        stage(As, A_KM, va);
+        stage(Bs, B_KN, vb);
         __syncthreads();
-        // lane l supplies row (l % 16) and k = 8 * (l / 16) .. + 7
+        if (k0 + BK < g.K) {  // next step's tiles, in flight during the MFMAs
+            load(g.A, g.lda, m0, A_KM, k0 + BK, va);
+            load(g.B, g.ldb, n0, B_KN, k0 + BK, vb);
+        }
+        // lane l supplies row (l % 16) and k = 8 * (l / 16) .. + 7 of each
+        // 32-wide slice
         const int r = lane & 15, kq = (lane >> 4) * 8;
-        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            a[i] = *(const bf16x8 *)&As[wm * 32 + i * 16 + r][kq];
+        for (int ks = 0; ks < BK; ks += 32) {
+            bf16x8 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            b[j] = *(const bf16x8 *)&Bs[wn * 32 + j * 16 + r][kq];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                a[i] = *(const bf16x8 *)&As[wm * 32 + i * 16 + r][ks + kq];
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[j] = *(const bf16x8 *)&Bs[wn * 32 + j * 16 + r][ks + kq];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
     }
     // accumulator block layout: lane l holds column l % 16, rows 4 (l / 16) + 0..3
 #pragma unroll
@@ -144,9 +173,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 template <bool A_KM, bool B_KN, int EPI>
 static hipError_t gemm(const GemmArgs &g, hipStream_t s)
 {
-    if (g.M % kBM || g.N % kBN || g.K % kBK)
+    if (g.M % kBM || g.N % kBN || g.K % kBK || g.K <= 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gemm<A_KM, B_KN, EPI>), dim3(g.N / kBN, g.M / kBM), dim3(256), 0, s, g);
+    const dim3 grid(g.N / kBN, g.M / kBM);
+    if (g.K % kBKWide == 0)
+        hipLaunchKernelGGL((k_gemm<A_KM, B_KN, EPI, kBKWide>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm<A_KM, B_KN, EPI, kBK>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
