@@ -61,3 +61,35 @@ def test_null_arguments_are_rejected_without_a_device(libpath):
     assert b"required" in L.rd_last_error()
     assert L.forward_solve_batch(None, 1, None, None, None, None, None, None, None) == _lib.RD_EINVAL
     assert L.destroy_problem(None) == _lib.RD_OK
+
+
+def test_growth1d_null_arguments_are_rejected_without_a_device(libpath):
+    from paper_1605_04718_amd import _lib
+    L = _lib.lib()
+    assert L.g1d_init(None, None) == _lib.RD_EINVAL
+    assert L.g1d_forward_batch(None, 1, None, None, None, None, None) == _lib.RD_EINVAL
+    assert L.g1d_log_likelihood_batch(None, 1, None, None, None, None) == _lib.RD_EINVAL
+    assert L.g1d_mcmc_step_batch(None, None, 1, None) == _lib.RD_EINVAL
+    assert b"NULL" in L.rd_last_error()
+    assert L.g1d_destroy(None) == _lib.RD_OK
+
+
+def test_growth1d_descriptor_is_validated_before_any_device_call(libpath):
+    """n outside [2, 128] and a missing initial field are call errors that
+    need no device."""
+    import ctypes
+    import numpy as np
+    from paper_1605_04718_amd import _lib
+    L = _lib.lib()
+    u = np.ones(200)
+    d = _lib.G1dDesc()
+    d.n, d.n_steps, d.tau, d.rho_T, d.max_batch = 129, 10, 1e-4, 1.8, 4
+    d.theta[:] = [0.1, 0.9, 1000.0, 10.0]
+    d.u0 = d.v0 = u.ctypes.data_as(_lib.c_dp)
+    h = ctypes.c_void_p()
+    assert L.g1d_init(ctypes.byref(d), ctypes.byref(h)) == _lib.RD_EINVAL
+    assert b"n = 129" in L.rd_last_error()
+    d.n = 100
+    d.v0 = None
+    assert L.g1d_init(ctypes.byref(d), ctypes.byref(h)) == _lib.RD_EINVAL
+    assert b"u0 and v0" in L.rd_last_error()
