@@ -203,9 +203,12 @@ hipError_t record_solve_end(rd_problem *p, hipStream_t s, hipEvent_t start)
 // Enqueue: reset the queue head, then the persistent fused solve.
 // Without grid ids every item is of class `cls` (0 for the public calls;
 // the autotuner times each class on its own).
+// cost_iters (optional, [n][2]): CG iterations of each item's last solve;
+// a single-class launch then takes its items largest first.
 int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid_id,
                       const int *need, double *phi, int *status, int *iters, void *u_out,
-                      void *v_out, hipStream_t s, int cls = 0, int *steps_out = nullptr)
+                      void *v_out, hipStream_t s, int cls = 0, int *steps_out = nullptr,
+                      const int *cost_iters = nullptr)
 {
     if (n == 0)
         return RD_OK;
@@ -267,6 +270,9 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     HIP_TRY(launch_fill_u32(p->queue, 0u, 1, s));
     if (mixed) {
         HIP_TRY(launch_class_order(grid_id, n, p->desc.n_grids, p->rank, p->order_ws, s));
+        a.order = p->order_ws;
+    } else if (cost_iters && n <= kMaxCostOrder) {
+        HIP_TRY(launch_cost_order(n, need, cost_iters, p->order_ws, s));
         a.order = p->order_ws;
     }
     hipEvent_t e0;
@@ -357,8 +363,12 @@ int32_t enqueue_mcmc_step(rd_problem *p, const rd_chains *c, int mode, hipStream
             return fail(r, "surrogate evaluation failed: %s", hipGetErrorString(hipGetLastError()));
         HIP_TRY(launch_da_stage1(a, s));
     }
+    // iters_ws keeps, per chain, the iterations of its last solved proposal
+    // (items that are not solved leave their entry): the cost estimate of
+    // this step's proposal, which lies close to it
     int32_t r = enqueue_solve(p, c->n_chains, p->theta_prop, c->grid_id, p->need, p->ll_prop,
-                              p->status_ws, p->iters_ws, nullptr, nullptr, s);
+                              p->status_ws, p->iters_ws, nullptr, nullptr, s, 0, nullptr,
+                              p->iters_ws);
     if (r != RD_OK)
         return r;
     if (mode == RD_MODE_PLAIN)
@@ -503,9 +513,16 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     p->status_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->iters_ws = (int *)dmalloc(p, sizeof(int) * 2 * B, &err);
     p->pmh_gid = (int *)dmalloc(p, sizeof(int) * B, &err);
+    p->order_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     if (err != RD_OK) {
         destroy_problem(p);
         return err;
+    }
+    // no solve yet: every cost estimate is 0, and the first queue order is
+    // the identity
+    if (hipMemset(p->iters_ws, 0, sizeof(int) * 2 * B) != hipSuccess) {
+        destroy_problem(p);
+        return fail(RD_EHIP, "hipMemset of the iteration workspace failed");
     }
     if (hipMemcpy(p->grids_dev, p->grids_host.data(), sizeof(GridDev) * desc->n_grids,
                   hipMemcpyHostToDevice) != hipSuccess ||
@@ -551,7 +568,6 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
                 p->mixed_threads = it->second;
         }
         p->mixed_wpc = mixed_wgs_per_cu(desc->precision, p->mixed_threads);
-        p->order_ws = (int *)dmalloc(p, sizeof(int) * desc->max_batch, &err);
     }
     // cooperative tiles: group counters, partial sums and edge rows
     for (int g = 0; g < desc->n_grids; ++g) {

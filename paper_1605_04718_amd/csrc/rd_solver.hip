@@ -897,6 +897,54 @@ __global__ __launch_bounds__(1024) void k_class_order(const int *grid_id, int n,
         order[local[class_rank(rank, grid_id[i], n_grids)]++] = i;
 }
 
+// Queue order of a single-class launch: items by decreasing cost estimate
+// (the CG iterations of the item's last solve, both species), items that are
+// not solved last, ties in index order.  Solve costs are heavy-tailed (a few
+// parameters need tens of CG iterations per step where most need two or
+// three), and a persistent queue that meets its costliest items last ends
+// with most workgroups idle; largest first bounds that tail by the smallest
+// items.  Only the order in which workgroups take items changes, not what an
+// item computes.  One workgroup: bitonic sort of (inverted key, index) in LDS.
+__global__ __launch_bounds__(1024) void k_cost_order(int n, const int *need, const int *iters,
+                                                     int *order)
+{
+    __shared__ unsigned long long s[kMaxCostOrder];
+    int np = 1;
+    while (np < n)
+        np <<= 1;
+    for (int i = threadIdx.x; i < np; i += 1024) {
+        unsigned long long v = ~0ull;  // padding sorts after every item
+        if (i < n) {
+            unsigned key = 0xFFFFFFFFu;  // not solved: last
+            if (!need || need[i]) {
+                const long long c = (long long)iters[2 * i] + (long long)iters[2 * i + 1];
+                const unsigned cc = c < 0 ? 0u : (c > 0x7FFFFFFF ? 0x7FFFFFFFu : (unsigned)c);
+                key = 0x7FFFFFFFu - cc;  // larger cost sorts first
+            }
+            v = ((unsigned long long)key << 32) | (unsigned)i;
+        }
+        s[i] = v;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += 1024) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long x = s[i], y = s[l];
+                    if ((x > y) == ((i & k) == 0)) {
+                        s[i] = y;
+                        s[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n; i += 1024)
+        order[i] = (int)(unsigned)(s[i] & 0xFFFFFFFFull);
+}
+
 // ---------------------------------------------------------------------------
 // Cooperative solve of a large grid (256 x 256) by a group of G workgroups.
 //
@@ -1937,6 +1985,14 @@ int mixed_wgs_per_cu(int precision, int threads)
                               : occupancy(k_solve_mixed<1024, float>, 1024);
     return threads == 512 ? occupancy(k_solve_mixed<512, double>, 512)
                           : occupancy(k_solve_mixed<1024, double>, 1024);
+}
+
+hipError_t launch_cost_order(int n, const int *need, const int *iters, int *order, hipStream_t s)
+{
+    if (n <= 0 || n > kMaxCostOrder)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, s, n, need, iters, order);
+    return hipGetLastError();
 }
 
 hipError_t launch_class_order(const int *grid_id, int n, int n_grids, const RankTable &rank,
