@@ -364,8 +364,8 @@ int32_t enqueue_mcmc_step(rd_problem *p, const rd_chains *c, int mode, hipStream
         HIP_TRY(launch_da_stage1(a, s));
     }
     // iters_ws keeps, per chain, the iterations of its last solved proposal
-    // (items that are not solved leave their entry): the cost estimate of
-    // this step's proposal, which lies close to it
+    // (items that are not solved leave their entry; -1 before the first):
+    // the cost estimate of this step's proposal, which lies close to it
     int32_t r = enqueue_solve(p, c->n_chains, p->theta_prop, c->grid_id, p->need, p->ll_prop,
                               p->status_ws, p->iters_ws, nullptr, nullptr, s, 0, nullptr,
                               p->iters_ws);
@@ -518,9 +518,9 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         destroy_problem(p);
         return err;
     }
-    // no solve yet: every cost estimate is 0, and the first queue order is
-    // the identity
-    if (hipMemset(p->iters_ws, 0, sizeof(int) * 2 * B) != hipSuccess) {
+    // no solve yet: every cost estimate is unknown (-1), and the first queue
+    // order is the identity
+    if (hipMemset(p->iters_ws, 0xFF, sizeof(int) * 2 * B) != hipSuccess) {
         destroy_problem(p);
         return fail(RD_EHIP, "hipMemset of the iteration workspace failed");
     }

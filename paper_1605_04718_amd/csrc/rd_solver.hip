@@ -747,6 +747,10 @@ __device__ __forceinline__ int item_grid(const SolveArgs &a, int c)
         a.status[c] = kStBadGrid;
         if (a.phi)
             a.phi[c] = __builtin_inf();
+        if (a.iters) {
+            a.iters[2 * c] = 0;
+            a.iters[2 * c + 1] = 0;
+        }
     }
     return -1;
 }
@@ -898,8 +902,10 @@ __global__ __launch_bounds__(1024) void k_class_order(const int *grid_id, int n,
 }
 
 // Queue order of a single-class launch: items by decreasing cost estimate
-// (the CG iterations of the item's last solve, both species), items that are
-// not solved last, ties in index order.  Solve costs are heavy-tailed (a few
+// (the CG iterations of the item's last solve, both species; a negative
+// count means no solve yet, and such items go first, since any of them may
+// be among the costliest), items that are not solved last, ties in index
+// order.  Solve costs are heavy-tailed (a few
 // parameters need tens of CG iterations per step where most need two or
 // three), and a persistent queue that meets its costliest items last ends
 // with most workgroups idle; largest first bounds that tail by the smallest
@@ -917,8 +923,9 @@ __global__ __launch_bounds__(1024) void k_cost_order(int n, const int *need, con
         if (i < n) {
             unsigned key = 0xFFFFFFFFu;  // not solved: last
             if (!need || need[i]) {
-                const long long c = (long long)iters[2 * i] + (long long)iters[2 * i + 1];
-                const unsigned cc = c < 0 ? 0u : (c > 0x7FFFFFFF ? 0x7FFFFFFFu : (unsigned)c);
+                const int iu = iters[2 * i], iv = iters[2 * i + 1];
+                const long long c = (long long)iu + (long long)iv;
+                const unsigned cc = (iu < 0 || iv < 0 || c > 0x7FFFFFFF) ? 0x7FFFFFFFu : (unsigned)c;
                 key = 0x7FFFFFFFu - cc;  // larger cost sorts first
             }
             v = ((unsigned long long)key << 32) | (unsigned)i;
