@@ -102,6 +102,7 @@ struct rd_problem {
     int *status_ws = nullptr;
     int *pmh_gid = nullptr;   // [max_batch] item classes of a parallel-MH batch
     int *iters_ws = nullptr;
+    int *cost_ws = nullptr;      // [max_batch] per-chain solve cost estimate (-1: none yet)
     uint64_t *ctr = nullptr;
     void *gws = nullptr;     // per-workgroup solve slots
     size_t gws_stride = 0;
@@ -203,12 +204,12 @@ hipError_t record_solve_end(rd_problem *p, hipStream_t s, hipEvent_t start)
 // Enqueue: reset the queue head, then the persistent fused solve.
 // Without grid ids every item is of class `cls` (0 for the public calls;
 // the autotuner times each class on its own).
-// cost_iters (optional, [n][2]): CG iterations of each item's last solve;
-// a single-class launch then takes its items largest first.
+// cost (optional, [n]): per-item cost estimates (negative: unknown); a
+// single-class launch then takes its items largest first.
 int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid_id,
                       const int *need, double *phi, int *status, int *iters, void *u_out,
                       void *v_out, hipStream_t s, int cls = 0, int *steps_out = nullptr,
-                      const int *cost_iters = nullptr)
+                      const int *cost = nullptr)
 {
     if (n == 0)
         return RD_OK;
@@ -271,8 +272,8 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     if (mixed) {
         HIP_TRY(launch_class_order(grid_id, n, p->desc.n_grids, p->rank, p->order_ws, s));
         a.order = p->order_ws;
-    } else if (cost_iters && n <= kMaxCostOrder) {
-        HIP_TRY(launch_cost_order(n, need, cost_iters, p->order_ws, s));
+    } else if (cost && n <= kMaxCostOrder) {
+        HIP_TRY(launch_cost_order(n, need, cost, p->order_ws, s));
         a.order = p->order_ws;
     }
     hipEvent_t e0;
@@ -363,14 +364,15 @@ int32_t enqueue_mcmc_step(rd_problem *p, const rd_chains *c, int mode, hipStream
             return fail(r, "surrogate evaluation failed: %s", hipGetErrorString(hipGetLastError()));
         HIP_TRY(launch_da_stage1(a, s));
     }
-    // iters_ws keeps, per chain, the iterations of its last solved proposal
-    // (items that are not solved leave their entry; -1 before the first):
-    // the cost estimate of this step's proposal, which lies close to it
+    // cost_ws keeps, per chain, a decaying maximum of the CG iterations of
+    // its solved proposals (-1 before the first): the cost estimate of this
+    // step's proposal, which lies close to them
     int32_t r = enqueue_solve(p, c->n_chains, p->theta_prop, c->grid_id, p->need, p->ll_prop,
                               p->status_ws, p->iters_ws, nullptr, nullptr, s, 0, nullptr,
-                              p->iters_ws);
+                              p->cost_ws);
     if (r != RD_OK)
         return r;
+    HIP_TRY(launch_note_cost(c->n_chains, p->need, p->iters_ws, p->cost_ws, s));
     if (mode == RD_MODE_PLAIN)
         HIP_TRY(launch_accept(a, s));
     else
@@ -514,15 +516,16 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     p->iters_ws = (int *)dmalloc(p, sizeof(int) * 2 * B, &err);
     p->pmh_gid = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->order_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
+    p->cost_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     if (err != RD_OK) {
         destroy_problem(p);
         return err;
     }
     // no solve yet: every cost estimate is unknown (-1), and the first queue
     // order is the identity
-    if (hipMemset(p->iters_ws, 0xFF, sizeof(int) * 2 * B) != hipSuccess) {
+    if (hipMemset(p->cost_ws, 0xFF, sizeof(int) * B) != hipSuccess) {
         destroy_problem(p);
-        return fail(RD_EHIP, "hipMemset of the iteration workspace failed");
+        return fail(RD_EHIP, "hipMemset of the cost workspace failed");
     }
     if (hipMemcpy(p->grids_dev, p->grids_host.data(), sizeof(GridDev) * desc->n_grids,
                   hipMemcpyHostToDevice) != hipSuccess ||

@@ -92,10 +92,13 @@ hipError_t launch_solve_mixed(int precision, int threads, const SolveArgs &a, in
                               hipStream_t s);
 hipError_t launch_class_order(const int *grid_id, int n, int n_grids, const RankTable &rank,
                               int *order, hipStream_t s);
-// Largest-first queue order of a single-class launch from the CG iterations
-// of each item's last solve (iters [n][2]); need may be null.  n <= kMaxCostOrder.
+// Largest-first queue order of a single-class launch from per-item cost
+// estimates (cost [n], negative = unknown); need may be null.
+// n <= kMaxCostOrder.  launch_note_cost updates the estimates of the solved
+// items from a solve's CG iterations (iters [n][2]).
 constexpr int kMaxCostOrder = 8192;
-hipError_t launch_cost_order(int n, const int *need, const int *iters, int *order, hipStream_t s);
+hipError_t launch_cost_order(int n, const int *need, const int *cost, int *order, hipStream_t s);
+hipError_t launch_note_cost(int n, const int *need, const int *iters, int *cost, hipStream_t s);
 bool mixed_supported(int n, int precision, int threads);
 bool tile_coop(int n, int precision, int cpt);  // a group of workgroups per item
 size_t mixed_slot_bytes(int n, int precision, int threads);

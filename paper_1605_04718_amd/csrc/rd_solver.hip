@@ -902,16 +902,15 @@ __global__ __launch_bounds__(1024) void k_class_order(const int *grid_id, int n,
 }
 
 // Queue order of a single-class launch: items by decreasing cost estimate
-// (the CG iterations of the item's last solve, both species; a negative
-// count means no solve yet, and such items go first, since any of them may
-// be among the costliest), items that are not solved last, ties in index
-// order.  Solve costs are heavy-tailed (a few
+// (cost[i], CG iterations as kept by k_note_cost; a negative estimate means
+// no solve yet, and such items go first, since any of them may be among the
+// costliest), items that are not solved last, ties in index order.  Solve costs are heavy-tailed (a few
 // parameters need tens of CG iterations per step where most need two or
 // three), and a persistent queue that meets its costliest items last ends
 // with most workgroups idle; largest first bounds that tail by the smallest
 // items.  Only the order in which workgroups take items changes, not what an
 // item computes.  One workgroup: bitonic sort of (inverted key, index) in LDS.
-__global__ __launch_bounds__(1024) void k_cost_order(int n, const int *need, const int *iters,
+__global__ __launch_bounds__(1024) void k_cost_order(int n, const int *need, const int *cost,
                                                      int *order)
 {
     __shared__ unsigned long long s[kMaxCostOrder];
@@ -923,9 +922,8 @@ __global__ __launch_bounds__(1024) void k_cost_order(int n, const int *need, con
         if (i < n) {
             unsigned key = 0xFFFFFFFFu;  // not solved: last
             if (!need || need[i]) {
-                const int iu = iters[2 * i], iv = iters[2 * i + 1];
-                const long long c = (long long)iu + (long long)iv;
-                const unsigned cc = (iu < 0 || iv < 0 || c > 0x7FFFFFFF) ? 0x7FFFFFFFu : (unsigned)c;
+                const int c = cost[i];
+                const unsigned cc = c < 0 ? 0x7FFFFFFFu : (unsigned)c;
                 key = 0x7FFFFFFFu - cc;  // larger cost sorts first
             }
             v = ((unsigned long long)key << 32) | (unsigned)i;
@@ -950,6 +948,22 @@ __global__ __launch_bounds__(1024) void k_cost_order(int n, const int *need, con
     }
     for (int i = threadIdx.x; i < n; i += 1024)
         order[i] = (int)(unsigned)(s[i] & 0xFFFFFFFFull);
+}
+
+// The cost estimate of each solved item after a solve: its CG iterations
+// (both species), or 7/8 of the previous estimate when that is larger.  A
+// decaying maximum keeps a chain that was costly recently near the front of
+// the queue (a chain near the stiff edge of the prior jumps between cheap and
+// costly solves) and forgets it after a few cheap ones.
+__global__ void k_note_cost(int n, const int *need, const int *iters, int *cost)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || (need && !need[c]))
+        return;
+    const long long s = (long long)iters[2 * c] + (long long)iters[2 * c + 1];
+    const int it = s < 0 ? 0 : (s > 0x7FFFFFFF ? 0x7FFFFFFF : (int)s);
+    const int e = cost[c];
+    cost[c] = e < 0 ? it : max(it, e - (e >> 3));
 }
 
 // ---------------------------------------------------------------------------
@@ -1994,11 +2008,19 @@ int mixed_wgs_per_cu(int precision, int threads)
                           : occupancy(k_solve_mixed<1024, double>, 1024);
 }
 
-hipError_t launch_cost_order(int n, const int *need, const int *iters, int *order, hipStream_t s)
+hipError_t launch_cost_order(int n, const int *need, const int *cost, int *order, hipStream_t s)
 {
     if (n <= 0 || n > kMaxCostOrder)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, s, n, need, iters, order);
+    hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, s, n, need, cost, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_note_cost(int n, const int *need, const int *iters, int *cost, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_note_cost, dim3((n + 255) / 256), dim3(256), 0, s, n, need, iters, cost);
     return hipGetLastError();
 }
 
