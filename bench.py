@@ -69,10 +69,11 @@ FLOP_CG_ITER = 20.0
 FLOP_SETUP = 38.0
 # HBM bytes of the fused solve kernel from two rocprofv3 PMC passes over the
 # timed step of `bench.py --steps 1 --warmup 0 --no-da --no-cpu-baseline
-# --no-mixed` (3831 solves): FETCH_SIZE 3 500 968 941 KiB x 2.00 +
-# WRITE_SIZE 7 460 487 633 KiB x 1.00 (factors from a 256 MiB copy), per
+# --no-mixed` (3831 solves): FETCH_SIZE 3 501 785 479 KiB x 2.00 +
+# WRITE_SIZE 7 460 049 918 KiB x 1.00 (factors from a 256 MiB copy), per
 # solve-step.  Valid only for the kernel version and tile it was measured on
-# (the one-pass residual of hi and lo).
+# (the one-pass residual of hi and lo; the queue order does not change what
+# a solve reads or writes).
 MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 483253.3208332028}
 
 
@@ -530,7 +531,7 @@ def growth1d_leg(args, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chains", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
