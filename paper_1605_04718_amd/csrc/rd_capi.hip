@@ -523,9 +523,10 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     }
     // no solve yet: every cost estimate is unknown (-1), and the first queue
     // order is the identity
-    if (hipMemset(p->cost_ws, 0xFF, sizeof(int) * B) != hipSuccess) {
+    if (hipMemset(p->cost_ws, 0xFF, sizeof(int) * B) != hipSuccess ||
+        hipMemset(p->iters_ws, 0, sizeof(int) * 2 * B) != hipSuccess) {
         destroy_problem(p);
-        return fail(RD_EHIP, "hipMemset of the cost workspace failed");
+        return fail(RD_EHIP, "hipMemset of the cost and iteration workspaces failed");
     }
     if (hipMemcpy(p->grids_dev, p->grids_host.data(), sizeof(GridDev) * desc->n_grids,
                   hipMemcpyHostToDevice) != hipSuccess ||

@@ -1665,6 +1665,10 @@ __device__ void coop_drain(const SolveArgs &a, bool prefix_only, unsigned *queue
             a.status[c] = bad ? kStBadGrid : kStNotConverged;
             if (a.phi)
                 a.phi[c] = __builtin_inf();
+            if (a.iters) {
+                a.iters[2 * c] = 0;
+                a.iters[2 * c + 1] = 0;
+            }
         }
         if (threadIdx.x == 0)
             *s_item = (int)atomicAdd(queue, 1u);
@@ -1729,6 +1733,10 @@ __device__ void coop_run(const SolveArgs &a, bool prefix_only, float *P, float *
                 a.status[c] = kStBadGrid;
                 if (a.phi)
                     a.phi[c] = __builtin_inf();
+                if (a.iters) {
+                    a.iters[2 * c] = 0;
+                    a.iters[2 * c + 1] = 0;
+                }
             }
             continue;
         }
