@@ -100,3 +100,24 @@ def test_loglik_zero_steps_is_the_misfit_of_the_initial_fields():
         pytest.approx(0.5 * n * 0.01 / 0.25, rel=1e-14)
     assert g1.loglik_beta(th, (0.1, 0.2, 0.3), 1.8, u0, v0, 1e-4, 0, y, 0.5, obs=3) == \
         pytest.approx(0.5 * n * 0.05 / 0.25, rel=1e-14)
+
+
+def test_total_mass_follows_the_dilution_law_without_reactions():
+    """gamma = 0: the mirror-boundary Laplacian sums to zero over the cells,
+    so summing the step gives sum(u') (1/tau + rho'/rho) = sum(u)/tau exactly
+    for any field (a wrong boundary row, a dropped or flipped dilution term
+    breaks it); likewise for v."""
+    theta = (0.3, 0.2, 0.0, 7.0)
+    n, tau, steps, T, rho_T = 45, 2e-3, 30, 0.06, 2.2
+    beta = (1.5, -0.4, 0.3)
+    rng = np.random.default_rng(4)
+    u, v = rng.uniform(0.5, 1.5, n), rng.uniform(0.2, 0.8, n)
+    mu, mv = u.sum(), v.sum()
+    m0 = mu
+    for s in range(steps):
+        rho, drho = g1.rho_poly(beta, rho_T, T, s * tau)
+        u, v = g1.imex_step(theta, u, v, tau, rho, drho)
+        mu /= 1.0 + tau * drho / rho
+        mv /= 1.0 + tau * drho / rho
+        assert u.sum() == pytest.approx(mu, rel=1e-12) and v.sum() == pytest.approx(mv, rel=1e-12)
+    assert g1.rho_poly(beta, rho_T, T, 0.0)[1] > 0 and mu < 0.5 * m0  # growth dilutes
