@@ -55,7 +55,8 @@ enum {
     RD_EINVAL = -1,       /* bad argument, shape or size */
     RD_EHIP = -2,         /* a HIP runtime call failed */
     RD_ENOMEM = -3,       /* device allocation failed */
-    RD_EUNSUPPORTED = -4  /* valid request this build does not implement */
+    RD_EUNSUPPORTED = -4, /* valid request this build does not implement */
+    RD_ETIMEOUT = -5      /* rd_check_solves: a cooperative group wait gave up */
 };
 
 /* Per-item status bits. */
@@ -65,7 +66,12 @@ enum {
     RD_ST_NONFINITE = 4,     /* NaN/Inf in a field or reduction */
     RD_ST_OUT_OF_PRIOR = 8,  /* proposal outside the prior box: not solved */
     RD_ST_BAD_GRID = 16,     /* grid_id outside [0, n_grids): not solved */
-    RD_ST_NOT_STEADY = 32    /* steady-state stopping: n_steps reached first */
+    RD_ST_NOT_STEADY = 32,   /* steady-state stopping: n_steps reached first */
+    RD_ST_GROUP_TIMEOUT = 64 /* 256 x 256 cooperative solve: a workgroup of the
+                                item's group gave up waiting for the others (a
+                                scheduling failure, not a numerical one); the
+                                item is not solved and rd_check_solves reports
+                                RD_ETIMEOUT */
 };
 
 enum { RD_PRECISION_FP32 = 0, RD_PRECISION_FP64 = 1 };
@@ -359,6 +365,28 @@ int32_t rd_mixed_threads(const rd_problem *p, int32_t *threads);
  * reset = 1 clears after reading.  Timing is recorded only while enabled. */
 int32_t rd_solver_timing(rd_problem *p, int32_t enable, double *ms_total, int64_t *launches,
                          int32_t reset);
+
+/* Synchronises the device and reports whether any cooperative workgroup
+ * (the 256 x 256 FP32 tile, alone or inside a mixed batch) gave up a bounded
+ * group wait since the problem was created or last reset.  Such a wait ends
+ * after 10 s only when a member of the group can never arrive (not while
+ * every member is resident, which the launch guarantees); its items carry
+ * RD_ST_GROUP_TIMEOUT.  Batch calls never synchronise, so this is where the
+ * condition becomes a call error.
+ *   group_timeouts host int64 out (may be NULL): members that gave up
+ *   reset = 1 clears the count after reading.
+ * Returns RD_OK, RD_ETIMEOUT (count > 0; rd_last_error has the count),
+ * RD_EINVAL or RD_EHIP. */
+int32_t rd_check_solves(rd_problem *p, int64_t *group_timeouts, int32_t reset);
+
+/* Test hook for the failure path above: the bound of a cooperative group
+ * wait in 100 MHz real-time-counter ticks (<= 0: the 10 s default), and a
+ * delay (ticks, <= 1e8) that member 1 of every group sleeps before the
+ * group's first exchange (0: none).  A delay well above the bound makes the
+ * other members give up, so a test can drive the whole failure path from the
+ * host while every kernel still runs to its end.  Applies to later batch
+ * calls of this problem only.  Errors: RD_EINVAL. */
+int32_t rd_set_coop_wait(rd_problem *p, int64_t wait_ticks, int64_t stall_ticks);
 
 const char *rd_status_string(int32_t status_or_error);
 const char *rd_last_error(void);

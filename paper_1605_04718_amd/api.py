@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Chains, GridDesc, ProblemDesc, check, lib
+from ._lib import RD_ETIMEOUT, RD_OK, Chains, GridDesc, ProblemDesc, check, lib
 
 PLAIN, DA = _lib.MODE_PLAIN, _lib.MODE_DA
 FP32, FP64 = _lib.PRECISION_FP32, _lib.PRECISION_FP64
@@ -315,6 +315,27 @@ class Problem:
         t = ctypes.c_int32()
         check(lib().rd_mixed_threads(self.h, ctypes.byref(t)), "rd_mixed_threads")
         return t.value
+
+    def check_solves(self, reset=True):
+        """Synchronises and raises RDError (RD_ETIMEOUT) when a cooperative
+        group wait gave up since the last check; returns the count (0)."""
+        n = ctypes.c_int64()
+        check(lib().rd_check_solves(self.h, ctypes.byref(n), int(reset)), "rd_check_solves")
+        return n.value
+
+    def group_timeouts(self, reset=True):
+        """Members whose cooperative group wait gave up (no exception)."""
+        n = ctypes.c_int64()
+        code = lib().rd_check_solves(self.h, ctypes.byref(n), int(reset))
+        if code not in (RD_OK, RD_ETIMEOUT):
+            check(code, "rd_check_solves")
+        return n.value
+
+    def set_coop_wait(self, wait_ticks=0, stall_ticks=0):
+        """Test hook: bound of a cooperative group wait and a first-exchange
+        delay of member 1 of every group (100 MHz ticks; 0, 0 restores)."""
+        check(lib().rd_set_coop_wait(self.h, int(wait_ticks), int(stall_ticks)),
+              "rd_set_coop_wait")
 
     def solver_timing(self, enable=True, reset=False):
         ms = ctypes.c_double()

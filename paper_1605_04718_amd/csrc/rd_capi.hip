@@ -111,6 +111,11 @@ struct rd_problem {
     int coop_groups = 0;
     int coop_wpc = 0;        // resident cooperative workgroups per CU
     int mixed_coop_wpc = 0;  // resident workgroups per CU of the fused mixed launch
+    // cooperative waits: bound (100 MHz ticks), test-hook stall, and the
+    // device count of members whose wait gave up since the last check
+    unsigned long long coop_wait_ticks = 1000000000ull;
+    unsigned long long coop_stall_ticks = 0;
+    unsigned *coop_timeouts = nullptr;
     // timing of the fused solve kernel
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -243,6 +248,9 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     a.coop_groups = p->coop_groups;
     a.steady_tt = p->desc.steady_tol > 0.0 ? p->desc.steady_tol * p->desc.dt : 0.0;
     a.steps_out = steps_out;
+    a.coop_wait_ticks = p->coop_wait_ticks;
+    a.coop_stall_ticks = p->coop_stall_ticks;
+    a.coop_timeouts = p->coop_timeouts;
     const TileChoice t = p->tile[g];
     // wgs_per_cu was queried when the tile was chosen: no runtime query may
     // run here, since this is also called while a stream is being captured.
@@ -517,6 +525,7 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     p->pmh_gid = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->order_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->cost_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
+    p->coop_timeouts = (unsigned *)dmalloc(p, 64, &err);
     if (err != RD_OK) {
         destroy_problem(p);
         return err;
@@ -524,7 +533,8 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     // no solve yet: every cost estimate is unknown (-1), and the first queue
     // order is the identity
     if (hipMemset(p->cost_ws, 0xFF, sizeof(int) * B) != hipSuccess ||
-        hipMemset(p->iters_ws, 0, sizeof(int) * 2 * B) != hipSuccess) {
+        hipMemset(p->iters_ws, 0, sizeof(int) * 2 * B) != hipSuccess ||
+        hipMemset(p->coop_timeouts, 0, 64) != hipSuccess) {
         destroy_problem(p);
         return fail(RD_EHIP, "hipMemset of the cost and iteration workspaces failed");
     }
@@ -1091,6 +1101,7 @@ extern "C" int32_t rd_set_tile(rd_problem *p, int32_t grid, int32_t cpt)
     // the workspace was sized for every supported tile of this class
     p->tile[grid] = TileChoice{cpt, n * n / cpt};
     p->wgs_per_cu[grid] = solve_wgs_per_cu(n, p->desc.precision, cpt);
+    drop_graphs(p);  // captured steps launch with the tile of their capture
     return RD_OK;
 }
 
@@ -1102,6 +1113,38 @@ extern "C" int32_t rd_set_mixed_threads(rd_problem *p, int32_t threads)
         return fail(RD_EINVAL, "threads must be 512 or 1024, got %d", threads);
     p->mixed_threads = threads;
     p->mixed_wpc = mixed_wgs_per_cu(p->desc.precision, threads);
+    drop_graphs(p);  // captured steps launch with the shape of their capture
+    return RD_OK;
+}
+
+extern "C" int32_t rd_check_solves(rd_problem *p, int64_t *group_timeouts, int32_t reset)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    HIP_TRY(hipDeviceSynchronize());
+    unsigned count = 0;
+    HIP_TRY(hipMemcpy(&count, p->coop_timeouts, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (group_timeouts)
+        *group_timeouts = (int64_t)count;
+    if (reset && count)
+        HIP_TRY(hipMemset(p->coop_timeouts, 0, sizeof(unsigned)));
+    if (count)
+        return fail(RD_ETIMEOUT,
+                    "%u cooperative workgroup(s) gave up a group wait: the items they served "
+                    "carry RD_ST_GROUP_TIMEOUT (Phi = +inf)",
+                    count);
+    return RD_OK;
+}
+
+extern "C" int32_t rd_set_coop_wait(rd_problem *p, int64_t wait_ticks, int64_t stall_ticks)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    if (wait_ticks < 0 || stall_ticks < 0 || stall_ticks > 100000000)
+        return fail(RD_EINVAL, "wait_ticks >= 0 and 0 <= stall_ticks <= 1e8 required");
+    p->coop_wait_ticks = wait_ticks > 0 ? (unsigned long long)wait_ticks : 1000000000ull;
+    p->coop_stall_ticks = (unsigned long long)stall_ticks;
+    drop_graphs(p);  // captured launches carry the old values
     return RD_OK;
 }
 
@@ -1148,12 +1191,14 @@ extern "C" const char *rd_status_string(int32_t s)
     case RD_EHIP: return "HIP runtime error";
     case RD_ENOMEM: return "out of device memory";
     case RD_EUNSUPPORTED: return "unsupported configuration";
+    case RD_ETIMEOUT: return "a cooperative group wait gave up";
     case RD_ST_NOT_CONVERGED: return "CG not converged";
     case RD_ST_BREAKDOWN: return "CG breakdown (operator not positive definite)";
     case RD_ST_NONFINITE: return "non-finite value";
     case RD_ST_OUT_OF_PRIOR: return "outside the prior box";
     case RD_ST_BAD_GRID: return "grid id outside [0, n_grids)";
     case RD_ST_NOT_STEADY: return "no steady state within n_steps";
+    case RD_ST_GROUP_TIMEOUT: return "cooperative group wait gave up (solve abandoned)";
     default: return "combination of status flags";
     }
 }

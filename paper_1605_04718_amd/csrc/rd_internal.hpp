@@ -11,7 +11,8 @@ enum : int {
     kStNonfinite = 4,
     kStOutOfPrior = 8,
     kStBadGrid = 16,
-    kStNotSteady = 32
+    kStNotSteady = 32,
+    kStGroupTimeout = 64
 };
 
 // One grid class as the kernels see it (device memory).
@@ -62,6 +63,10 @@ struct SolveArgs {
     int coop_wgs;            // class-ordered batch: nonzero when a cooperative
                              // launch serves the 256^2 items (the mixed launch
                              // then skips them)
+    unsigned long long coop_wait_ticks;   // bound of a group wait (100 MHz ticks)
+    unsigned long long coop_stall_ticks;  // test hook: member 1 of every group
+                                          // sleeps this long first (0: off)
+    unsigned *coop_timeouts;  // count of members whose group wait gave up (or null)
 };
 
 // Cooperative solve of one large grid by a group of workgroups.

@@ -993,10 +993,9 @@ __global__ void k_note_cost(int n, const int *need, const int *iters, int *cost)
 
 constexpr int kCoopStrip = kCoopN / kCoopG;              // 64 rows per member
 constexpr int kCoopR = kCoopStrip * kCoopN / kCoopThreads;  // 16 cells per thread
-// A group barrier gives up after this many ticks of the 100 MHz real-time
-// counter (10 s): far beyond any legitimate wait, it only bounds the damage
-// of a member that can never arrive.
-constexpr unsigned long long kCoopWaitTicks = 1000000000ull;
+// A group barrier gives up after SolveArgs::coop_wait_ticks ticks of the
+// 100 MHz real-time counter (10 s by default): far beyond any legitimate
+// wait, it only bounds the damage of a member that can never arrive.
 
 struct CoopArea {
     // header: the item queue; then per group: partial sums [2][G][4]
@@ -1020,6 +1019,7 @@ struct CoopCtx {
     unsigned seq;         // exchanges so far (this launch)
     int *fail;            // LDS flag: an exchange timed out
     double *gather;       // LDS [G * 4]
+    unsigned long long wait_ticks;  // bound of one wait
 
     __device__ double *partial(unsigned k) const
     {
@@ -1078,7 +1078,7 @@ __device__ __forceinline__ unsigned tag_of(double v)
 // return v holds the sums over the members, in member order (the same in
 // every member).  Also a group barrier: every coherent store that a thread
 // of any member issued before the exchange is visible after it.  Bounded:
-// after kCoopWaitTicks the member gives up and raises *fail, and a member
+// after x.wait_ticks the member gives up and raises *fail, and a member
 // that has failed no longer waits, so every exchange ends.
 template <int M>
 __device__ void coop_exchange(double (&v)[M], CoopCtx &x)
@@ -1113,7 +1113,7 @@ __device__ void coop_exchange(double (&v)[M], CoopCtx &x)
                 do {
                     __builtin_amdgcn_s_sleep(1);
                     got = coop_load(buf + lane_off(mm * 4 + j));
-                    if (__builtin_amdgcn_s_memrealtime() - t0 > kCoopWaitTicks) {
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > x.wait_ticks) {
                         *x.fail = 1;
                         break;
                     }
@@ -1181,7 +1181,7 @@ __device__ void coop_sum(double (&v)[M], double *red, CoopCtx &x)
                 do {
                     __builtin_amdgcn_s_sleep(1);
                     got = coop_load(buf + lane_off(mm * 4 + j));
-                    if (__builtin_amdgcn_s_memrealtime() - t0 > kCoopWaitTicks) {
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > x.wait_ticks) {
                         *x.fail = 1;
                         break;
                     }
@@ -1393,7 +1393,7 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
     int it = 0;
     while (st == 0 && (rr_pending || rr > tol2)) {
         if (*x.fail) {
-            st = kStNotConverged;
+            st = kStGroupTimeout;
             break;
         }
         if (it >= maxit) {
@@ -1486,7 +1486,7 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
         rr = rn;
     }
     if (*x.fail)
-        st |= kStNotConverged;
+        st |= kStGroupTimeout;
     it_acc += it;
     __syncthreads();
     return st;
@@ -1662,7 +1662,7 @@ __device__ void coop_drain(const SolveArgs &a, bool prefix_only, unsigned *queue
         if (prefix_only && (bad || uniform(a.grids[gid].n) != kCoopN))
             break;
         if (threadIdx.x == 0 && (!a.need || a.need[c])) {
-            a.status[c] = bad ? kStBadGrid : kStNotConverged;
+            a.status[c] = bad ? kStBadGrid : kStGroupTimeout;
             if (a.phi)
                 a.phi[c] = __builtin_inf();
             if (a.iters) {
@@ -1701,8 +1701,16 @@ __device__ void coop_run(const SolveArgs &a, bool prefix_only, float *P, float *
     x.seq = 0;
     x.fail = fail;
     x.gather = gather;
+    x.wait_ticks = a.coop_wait_ticks;
     unsigned *queue = (unsigned *)a.coop;
     float *slot = (float *)((char *)a.gws + (size_t)b * a.gws_stride);
+    if (a.coop_stall_ticks && member == 1) {
+        // Test hook (host-set): this member arrives late at the group's
+        // first exchange, so that the other members' bounded waits give up.
+        const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+        while (__builtin_amdgcn_s_memrealtime() - t0 < a.coop_stall_ticks)
+            __builtin_amdgcn_s_sleep(8);
+    }
     for (;;) {
         if (member == 0 && threadIdx.x == 0)
             *s_item = (int)atomicAdd(queue, 1u);
@@ -1742,6 +1750,10 @@ __device__ void coop_run(const SolveArgs &a, bool prefix_only, float *P, float *
         }
         solve_item_coop(a, c, a.grids[gid], P, stash, red, slot, x);
     }
+    // a member whose wait gave up is counted once per launch (host-visible)
+    if (*fail && threadIdx.x == 0 && a.coop_timeouts)
+        atomicAdd(a.coop_timeouts, 1u);
+    __syncthreads();  // every thread has read *fail before the LDS is reused
 }
 
 __global__ __launch_bounds__(kCoopThreads) void k_solve_coop(SolveArgs a)

@@ -206,3 +206,48 @@ def test_da_step_matches_oracle_decisions():
         compared += 1
     assert compared > C // 2
     p.close()
+
+
+def test_full_size_network_gradients_and_three_adam_steps_match_oracle():
+    """The surrogate at its full size (4 -> 4 x 512 -> 32^2 outputs, GELU)
+    and a batch of 1024: every hidden GEMM has K = 512 and the output layer
+    N = 1024, so the K loop runs several 128-wide steps with the next step's
+    tiles loaded during the current one.  Three consecutive training steps:
+    loss and all gradients against the FP64 oracle at the GPU's weights
+    before each step, and the weights after each step against the oracle's
+    Adam, whose moment state carries over the three steps (bias correction
+    at t = 1, 2, 3)."""
+    import torch
+    need_gpu()
+    p, *_ = small_problem(width=512, depth=4, out_side=32, n=128, steps=1, y=False)
+    rng = np.random.default_rng(7)
+    B = 1024
+    phi_all = inputs.box_draws(3 * B, LO, HI, seed=16)
+    x = omlp.scale_inputs(phi_all, LO, HI)
+    target_all = np.tanh(x @ rng.standard_normal((4, 1024))).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = {}
+    assert [W.shape for W, _ in host_params(p)] == [(512, 4), (512, 512), (512, 512), (512, 512),
+                                                    (1024, 512)]
+    for t in range(3):
+        phi = phi_all[t * B:(t + 1) * B]
+        target = target_all[t * B:(t + 1) * B]
+        before = host_params(p)
+        print(f"full-size surrogate: training step {t + 1} of 3, batch {B}", flush=True)
+        p.surrogate_train_step(torch.tensor(phi, device="cuda"),
+                               torch.tensor(target, device="cuda"), 1e-3, loss)
+        torch.cuda.synchronize()
+        grads = host_params(p, dir=2)
+        after = host_params(p)
+        y, cache = omlp.forward(before, omlp.scale_inputs(phi, LO, HI))
+        want_loss, dy = omlp.mse(y, target.astype(np.float64))
+        want_grads = omlp.backward(before, cache, dy)
+        assert loss.item() == pytest.approx(want_loss, rel=2e-2), (t, loss.item(), want_loss)
+        for li, ((gW, gb), (wW, wb)) in enumerate(zip(grads, want_grads)):
+            assert rel_l2(gW, wW) < 5e-2 and rel_l2(gb, wb) < 5e-2, (t, li, rel_l2(gW, wW),
+                                                                     rel_l2(gb, wb))
+        want_after = omlp.adam_step(before, grads, st, lr=1e-3)
+        assert st["t"] == t + 1
+        for (aW, ab), (wW, wb) in zip(after, want_after):
+            assert np.abs(aW - wW).max() < 2e-6 and np.abs(ab - wb).max() < 2e-6, t
+    p.close()

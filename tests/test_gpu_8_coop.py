@@ -102,3 +102,68 @@ def test_set_tile_rejects_unsupported():
     with pytest.raises(RDError):
         p.set_tile(1, STREAMED_CPT)
     p.close()
+
+
+def test_group_timeout_has_its_own_status_and_a_call_error():
+    """Forced from the host: member 1 of every group sleeps 2 ms before the
+    group's first exchange while the others wait at most 20 us, so every
+    bounded wait gives up and every kernel still runs to its end.  Every
+    256^2 item then carries RD_ST_GROUP_TIMEOUT (not the CG-cap bit), the
+    count turns into RD_ETIMEOUT at rd_check_solves, and with the defaults
+    restored the same batch solves."""
+    from paper_1605_04718_amd._lib import RD_ETIMEOUT, ST_GROUP_TIMEOUT, RDError
+    need_gpu()
+    steps, m = 3, 12
+    thetas = theta_batch(m, seed=53)
+    p, _, _ = make_problem(256, steps, precision=0, maxit=4000, max_batch=m)
+    p.set_tile(0, COOP_CPT)
+    assert p.check_solves() == 0
+    p.set_coop_wait(wait_ticks=2000, stall_ticks=200000)
+    print(f"coop 256 forced group timeout: {m} items, {steps} steps", flush=True)
+    _, _, st, _ = run(p, thetas)
+    assert np.all(st == ST_GROUP_TIMEOUT), st
+    with pytest.raises(RDError) as e:
+        p.check_solves()
+    assert e.value.code == RD_ETIMEOUT
+    assert p.group_timeouts() == 0  # the failing check reset the count
+    p.set_coop_wait(0, 0)
+    print(f"coop 256 after restoring the wait: {m} items", flush=True)
+    _, _, st, _ = run(p, thetas)
+    assert np.all(st == 0), st
+    assert p.check_solves() == 0
+    p.close()
+
+
+def test_group_timeout_in_the_fused_mixed_launch():
+    """The same forced give-up inside one launch over 256^2 and 64^2 items:
+    the 256^2 items carry RD_ST_GROUP_TIMEOUT, the 64^2 items (served by the
+    same workgroups afterwards) solve normally."""
+    import torch
+    from paper_1605_04718_amd._lib import ST_GROUP_TIMEOUT
+    from paper_1605_04718_amd.api import Grid, Problem
+    need_gpu()
+    steps = 3
+    grids = []
+    for n in (64, 256):
+        u0, v0 = inputs.initial_fields(n, THETA_TRUE[0], THETA_TRUE[1])
+        grids.append(Grid(n=n, u0=u0, v0=v0, y=None, sigma=1.0))
+    p = Problem(grids, TAU, steps, 1e-7, precision=0, cg_maxit=4000, max_batch=16)
+    p.set_mixed_threads(1024)
+    ids = np.array([0, 1] * 8, dtype=np.int32)
+    thetas = theta_batch(len(ids), seed=59)
+    th = torch.tensor(thetas, device="cuda")
+    gid = torch.tensor(ids, device="cuda")
+    p.set_coop_wait(wait_ticks=2000, stall_ticks=200000)
+    print("fused mixed launch, forced group timeout: 8 x 64^2 + 8 x 256^2", flush=True)
+    _, _, st, _ = p.forward_solve(th, grid_id=gid)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert np.all(st[ids == 1] == ST_GROUP_TIMEOUT), st
+    assert np.all(st[ids == 0] == 0), st
+    assert p.group_timeouts() > 0
+    p.set_coop_wait(0, 0)
+    _, _, st, _ = p.forward_solve(th, grid_id=gid)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    assert p.check_solves() == 0
+    p.close()
