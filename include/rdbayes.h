@@ -210,6 +210,10 @@ typedef struct {
     uint64_t step;         /* index of the next step; advanced by the calls */
     uint64_t trace_step0;  /* step index of trace row 0 */
     int32_t trace_rows;    /* rows the trace holds */
+    uint64_t *imex_steps;  /* dev [n] IMEX steps completed, summed over the chain's
+                              solves (a solve that fails at step s counts s), or NULL */
+    uint64_t *fail_bits;   /* dev [n][8] solves whose status has bit k set
+                              (RD_ST_* = 1 << k), or NULL */
 } rd_chains;
 
 /* n_steps Metropolis-Hastings steps (Sec. 2, Algorithm 1) of every chain.

@@ -55,7 +55,7 @@ class Chains(ctypes.Structure):
                 ("grid_id", c_vp), ("n_accept", c_vp), ("n_accept1", c_vp), ("n_solves", c_vp),
                 ("cg_iters", c_vp),
                 ("trace", c_vp), ("seed", c_u32), ("step", c_u64), ("trace_step0", c_u64),
-                ("trace_rows", c_i32)]
+                ("trace_rows", c_i32), ("imex_steps", c_vp), ("fail_bits", c_vp)]
 
 
 SYMBOLS = {

@@ -431,6 +431,8 @@ class ChainState:
     cg_iters: torch.Tensor | None = None
     trace: torch.Tensor | None = None
     trace_step0: int = 0
+    imex_steps: torch.Tensor | None = None   # [n] IMEX steps completed by the solves
+    fail_bits: torch.Tensor | None = None    # [n][8] solves with status bit k set
 
     @property
     def n(self):
@@ -446,7 +448,8 @@ class ChainState:
                    grid_id=grid_id, n_accept=z(), n_accept1=z(), n_solves=z(),
                    cg_iters=torch.zeros((n, 2), dtype=torch.int64, device=dev),
                    trace=(torch.zeros((trace_steps, n, 4), dtype=torch.float64, device=dev)
-                          if trace_steps else None), trace_step0=step)
+                          if trace_steps else None), trace_step0=step,
+                   imex_steps=z(), fail_bits=torch.zeros((n, 8), dtype=torch.int64, device=dev))
 
     def struct(self) -> Chains:
         c = Chains()
@@ -464,4 +467,6 @@ class ChainState:
         c.trace_step0 = self.trace_step0
         c.seed = self.seed
         c.step = self.step
+        c.imex_steps = _ptr(self.imex_steps)
+        c.fail_bits = _ptr(self.fail_bits)
         return c

@@ -64,6 +64,8 @@ long tune_key(int dev, int n, int prec)
 
 }  // namespace
 
+
+
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -103,6 +105,7 @@ struct rd_problem {
     int *pmh_gid = nullptr;   // [max_batch] item classes of a parallel-MH batch
     int *iters_ws = nullptr;
     int *cost_ws = nullptr;      // [max_batch] per-chain solve cost estimate (-1: none yet)
+    int *steps_ws = nullptr;     // [max_batch] IMEX steps each item of a sampler solve completed
     uint64_t *ctr = nullptr;
     void *gws = nullptr;     // per-workgroup solve slots
     size_t gws_stride = 0;
@@ -276,7 +279,7 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
                              p->coop_groups * kCoopG);
         a.coop_wgs = coop_grid >= 32 ? coop_grid : 0;
     }
-    HIP_TRY(launch_fill_u32(p->queue, 0u, 1, s));
+    HIP_TRY(launch_fill_u32(a.queue, 0u, 1, s));
     if (mixed) {
         HIP_TRY(launch_class_order(grid_id, n, p->desc.n_grids, p->rank, p->order_ws, s));
         a.order = p->order_ws;
@@ -354,6 +357,10 @@ SamplerArgs sampler_args(rd_problem *p, const rd_chains *c)
     a.n_solves = c->n_solves;
     a.cg_iters = c->cg_iters;
     a.iters = p->iters_ws;
+    a.imex_steps = c->imex_steps;
+    a.fail_bits = c->fail_bits;
+    a.steps = p->steps_ws;
+    a.status = p->status_ws;
     a.trace = c->trace;
     a.trace_rows = c->trace ? c->trace_rows : 0;
     return a;
@@ -376,7 +383,7 @@ int32_t enqueue_mcmc_step(rd_problem *p, const rd_chains *c, int mode, hipStream
     // its solved proposals (-1 before the first): the cost estimate of this
     // step's proposal, which lies close to them
     int32_t r = enqueue_solve(p, c->n_chains, p->theta_prop, c->grid_id, p->need, p->ll_prop,
-                              p->status_ws, p->iters_ws, nullptr, nullptr, s, 0, nullptr,
+                              p->status_ws, p->iters_ws, nullptr, nullptr, s, 0, p->steps_ws,
                               p->cost_ws);
     if (r != RD_OK)
         return r;
@@ -394,7 +401,8 @@ bool same_chains(const rd_chains &a, const rd_chains &b)
     return a.n_chains == b.n_chains && a.phi == b.phi && a.loglik == b.loglik &&
            a.loglik_sur == b.loglik_sur && a.grid_id == b.grid_id && a.n_accept == b.n_accept &&
            a.n_accept1 == b.n_accept1 && a.n_solves == b.n_solves && a.cg_iters == b.cg_iters &&
-           a.trace == b.trace && a.trace_rows == b.trace_rows && a.seed == b.seed;
+           a.trace == b.trace && a.trace_rows == b.trace_rows && a.seed == b.seed &&
+           a.imex_steps == b.imex_steps && a.fail_bits == b.fail_bits;
 }
 
 void drop_graphs(rd_problem *p)
@@ -526,6 +534,7 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     p->order_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->cost_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->coop_timeouts = (unsigned *)dmalloc(p, 64, &err);
+    p->steps_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     if (err != RD_OK) {
         destroy_problem(p);
         return err;
@@ -813,7 +822,10 @@ extern "C" int32_t accept_batch(rd_problem *p, rd_chains *chains, const double *
     a.phi_prop = const_cast<double *>(phi_prop);
     a.inside = const_cast<int *>(inside);
     a.loglik_prop = loglik_prop;
-    a.iters = nullptr;  // the caller's Phi did not come from this library's solve
+    // the caller's Phi did not come from this library's solve
+    a.iters = nullptr;
+    a.steps = nullptr;
+    a.status = nullptr;
     HIP_TRY(launch_accept(a, s));
     chains->step += 1;
     return RD_OK;
@@ -862,7 +874,7 @@ extern "C" int32_t pmh_step_batch(rd_problem *p, rd_chains *chains, int32_t n_pr
             gid = p->pmh_gid;
         }
         r = enqueue_solve(p, items, p->theta_prop, gid, p->inside, p->ll_prop, p->status_ws,
-                          p->iters_ws, nullptr, nullptr, s);
+                          p->iters_ws, nullptr, nullptr, s, 0, p->steps_ws);
         if (r != RD_OK)
             return r;
         HIP_TRY(launch_pmh_resample(a, n_prop, s));
@@ -907,6 +919,10 @@ extern "C" int32_t pmh_resample_batch(rd_problem *p, rd_chains *chains, int32_t 
         a.phi_prop = const_cast<double *>(phi_prop);
         a.inside = const_cast<int *>(inside);
         a.loglik_prop = loglik_prop;
+        // the caller's Phi did not come from this library's solve
+        a.iters = nullptr;
+        a.steps = nullptr;
+        a.status = nullptr;
         HIP_TRY(launch_pmh_resample(a, n_prop, s));
     }
     chains->step += (uint64_t)n_prop;

@@ -164,6 +164,28 @@ __global__ void k_pmh_propose(SamplerArgs a, int n_prop)
     a.inside[t] = in_support(a.cfg, p, d) ? 1 : 0;
 }
 
+// Counters of one solved proposal (item t of this step's solve) of chain c:
+// CG iterations, IMEX steps completed (a solve that failed at step s
+// completed s), and one count per status bit.
+__device__ __forceinline__ void note_solve(const SamplerArgs &a, int c, int t)
+{
+    if (a.n_solves)
+        a.n_solves[c] += 1;
+    if (a.cg_iters && a.iters) {
+        a.cg_iters[2 * c] += (uint64_t)a.iters[2 * t];
+        a.cg_iters[2 * c + 1] += (uint64_t)a.iters[2 * t + 1];
+    }
+    if (a.imex_steps && a.steps)
+        a.imex_steps[c] += (uint64_t)a.steps[t];
+    if (a.fail_bits && a.status) {
+        const int st = a.status[t];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((st >> k) & 1)
+                a.fail_bits[8 * c + k] += 1;
+    }
+}
+
 // Steps 3 and 4: the stationary distribution of A over the N + 1 points
 // (x_c and its N proposals).  A is a Metropolis chain with a uniform choice
 // among the other points, so by detailed balance that distribution is the
@@ -201,9 +223,10 @@ __global__ void k_pmh_resample(SamplerArgs a, int n_prop)
             const double l = logw(k);
             sum = sum + (l > -__builtin_inf() ? exp(l - mx) : 0.0);
         }
-    int moved = 0, last = 0, solved = 0;
+    int moved = 0, last = 0;
     for (int k = 0; k < n_prop; ++k)
-        solved += a.inside[c * n_prop + k] ? 1 : 0;
+        if (a.inside[c * n_prop + k])
+            note_solve(a, c, c * n_prop + k);
     for (int n = 0; n < n_prop; ++n) {
         int idx = 0;
         if (any) {
@@ -235,8 +258,6 @@ __global__ void k_pmh_resample(SamplerArgs a, int n_prop)
                 a.trace[(row * (uint64_t)a.n + c) * 4 + i] = src[i];
         }
     }
-    if (a.n_solves)
-        a.n_solves[c] += (uint64_t)solved;
     if (a.n_accept)
         a.n_accept[c] += (uint64_t)moved;
     if (last != 0) {
@@ -269,12 +290,7 @@ __global__ void k_accept(SamplerArgs a)
         const U32x4 w = stream_block(a.seed, (uint32_t)c, step, kPurposeAccept, 0);
         const double u = unit_open(w.x, w.y);
         acc = log(u) < (a.loglik[c] - a.loglik_prop[c]) + log_prior_ratio(a, c);
-        if (a.n_solves)
-            a.n_solves[c] += 1;
-        if (a.cg_iters && a.iters) {
-            a.cg_iters[2 * c] += (uint64_t)a.iters[2 * c];
-            a.cg_iters[2 * c + 1] += (uint64_t)a.iters[2 * c + 1];
-        }
+        note_solve(a, c, c);
     }
     if (acc) {
 #pragma unroll
@@ -325,12 +341,7 @@ __global__ void k_da_stage2(SamplerArgs a)
         const double u = unit_open(w.x, w.y);
         const double la = (a.loglik[c] - a.loglik_prop[c]) - (a.loglik_sur[c] - a.loglik_sur_prop[c]);
         acc = log(u) < la;
-        if (a.n_solves)
-            a.n_solves[c] += 1;
-        if (a.cg_iters && a.iters) {
-            a.cg_iters[2 * c] += (uint64_t)a.iters[2 * c];
-            a.cg_iters[2 * c + 1] += (uint64_t)a.iters[2 * c + 1];
-        }
+        note_solve(a, c, c);
     }
     if (acc) {
 #pragma unroll

@@ -35,6 +35,10 @@ struct SamplerArgs {
     uint64_t *n_solves;
     uint64_t *cg_iters;           // [n][2] accumulated CG iterations or null
     const int *iters;             // [n][2] CG iterations of this step's solves
+    uint64_t *imex_steps;         // [n] IMEX steps completed, summed over solves, or null
+    uint64_t *fail_bits;          // [n][8] solves with status bit k set, or null
+    const int *steps;             // [n] IMEX steps completed by this step's solves (or null)
+    const int *status;            // [n] status of this step's solves (or null)
     double *trace;                // [rows][n][4] or null; row = step - ctr[1]
     int trace_rows;
 };

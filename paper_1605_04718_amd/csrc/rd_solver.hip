@@ -751,6 +751,8 @@ __device__ __forceinline__ int item_grid(const SolveArgs &a, int c)
             a.iters[2 * c] = 0;
             a.iters[2 * c + 1] = 0;
         }
+        if (a.steps_out)
+            a.steps_out[c] = 0;
     }
     return -1;
 }
@@ -1669,6 +1671,8 @@ __device__ void coop_drain(const SolveArgs &a, bool prefix_only, unsigned *queue
                 a.iters[2 * c] = 0;
                 a.iters[2 * c + 1] = 0;
             }
+            if (a.steps_out)
+                a.steps_out[c] = 0;
         }
         if (threadIdx.x == 0)
             *s_item = (int)atomicAdd(queue, 1u);
@@ -1745,6 +1749,8 @@ __device__ void coop_run(const SolveArgs &a, bool prefix_only, float *P, float *
                     a.iters[2 * c] = 0;
                     a.iters[2 * c + 1] = 0;
                 }
+                if (a.steps_out)
+                    a.steps_out[c] = 0;
             }
             continue;
         }

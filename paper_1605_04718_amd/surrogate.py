@@ -56,6 +56,7 @@ def make_dataset(p, m, lo, hi, seed=inputs.SEED_DATASET, batch=4096, max_abs=10.
     squared-error fit while lying far from any posterior mass.  `phi`
     ([m, 4]) replaces the prior draws, e.g. draws around the posterior."""
     dev = torch.device("cuda")
+    batch = min(batch, p.max_batch)
     if phi is None:
         phi = inputs.box_draws(m, lo, hi, seed=seed)
     phi_all = torch.as_tensor(np.asarray(phi), dtype=torch.float64).to(dev)

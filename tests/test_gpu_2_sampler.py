@@ -218,3 +218,41 @@ def test_zz_graph_replay_matches_direct_launches():
     assert torch.equal(ch.phi, ch2.phi) and torch.equal(ch.loglik, ch2.loglik)
     assert torch.equal(ch.trace, ch2.trace)
     p.close()
+
+
+def test_chain_counters_count_completed_steps_and_status_bits():
+    """mcmc_step_batch's per-chain counters against the same proposals solved
+    through forward_solve_steady_batch: solves, completed IMEX steps (a solve
+    that stops at the CG cap in step s completed s) and one count per status
+    bit.  With a CG cap of 3 iterations the proposals fail part way; with the
+    default cap they complete."""
+    import torch
+    need_gpu()
+    C, steps = 256, 60
+    u0, v0 = inputs.initial_fields(32, 0.1, 0.9)
+    uo, _, _, _ = oracle.forward_solve(THETA_TRUE, u0, v0, TAU, steps, rtol=1e-12)
+    y, sigma = inputs.noisy_data(uo, 0.01)
+    phi = inputs.box_draws(C, LO, HI, seed=31)
+    for maxit in (3, 0):
+        p, _, _ = make_problem(32, steps, y=y, sigma=sigma, u0=u0, v0=v0, lo=LO, hi=HI,
+                               step=5 * STEP, max_batch=C, maxit=maxit)
+        ch = chains_at(phi, np.full(C, np.inf), seed=17)
+        prop, inside = p.propose(ch)
+        th = torch.tensor(inputs.to_natural(prop.cpu().numpy()), device="cuda")
+        _, _, st, _, nsteps = p.forward_solve_steady(th)
+        p.mcmc_step(ch, 1)
+        torch.cuda.synchronize()
+        inside, st, nsteps = inside.cpu().numpy() != 0, st.cpu().numpy(), nsteps.cpu().numpy()
+        failed = inside & (st != 0)
+        if maxit == 3:
+            assert failed.sum() > inside.sum() // 2
+        else:
+            assert failed.sum() < inside.sum() // 10
+        assert np.all(nsteps[inside & (st == 0)] == steps)
+        assert np.all(nsteps[failed] < steps)
+        assert np.array_equal(ch.n_solves.cpu().numpy(), inside.astype(np.int64))
+        assert np.array_equal(ch.imex_steps.cpu().numpy(), np.where(inside, nsteps, 0))
+        fb = ch.fail_bits.cpu().numpy()
+        for k in range(8):
+            assert np.array_equal(fb[:, k], (inside & ((st >> k) & 1 == 1)).astype(np.int64)), k
+        p.close()
