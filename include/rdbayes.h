@@ -184,6 +184,29 @@ int32_t log_likelihood_batch(rd_problem *p, int32_t n, const double *theta,
                              const int32_t *grid_id, double *phi, int32_t *status,
                              int32_t *cg_iters, void *stream);
 
+/* log_likelihood_batch without allocation, for callers that cannot
+ * allocate device memory at call time (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid it).  Same results as
+ * log_likelihood_batch with grid_id = NULL (the same kernels; items are
+ * independent, so the launch shape does not change any result), but the
+ * solve's scratch (queue head and one workspace slot per workgroup) lives
+ * in a file-scope device array of the library, 256 B + 64 MiB, one copy per
+ * device, held until the process ends, instead of the problem's workspace.
+ * The call allocates nothing (no hipMalloc, events or library routines that
+ * allocate) and enqueues a fill kernel and the solve kernel on `stream`.
+ * The launch uses at most as many workgroups as slots fit in the 64 MiB
+ * (256 at 128 x 128 FP32, 51 at 128 x 128 FP64), so it is never wider than
+ * the scratch; larger batches are served by the persistent queue.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, other problems, other threads) race and must
+ * be serialised by the caller.  One grid class only; the cooperative
+ * 256 x 256 FP32 tile is not served (select a streamed tile).
+ * Errors: RD_EINVAL (n outside [0, max_batch], NULL theta/phi/status, no
+ * data y), RD_EUNSUPPORTED (several grid classes, cooperative tile, a slot
+ * larger than the scratch), RD_EHIP. */
+int32_t log_likelihood_batch_noalloc(rd_problem *p, int32_t n, const double *theta, double *phi,
+                                     int32_t *status, int32_t *cg_iters, void *stream);
+
 /* Misfit of caller-supplied u fields against the data of their grid class
  * (the misfit kernel alone).  u dev [n][N*N] in the problem's precision. */
 int32_t field_misfit_batch(rd_problem *p, int32_t n, const void *u, const int32_t *grid_id,

@@ -63,6 +63,7 @@ SYMBOLS = {
     "destroy_problem": (c_i32, [c_vp]),
     "forward_solve_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "log_likelihood_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "log_likelihood_batch_noalloc": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "field_misfit_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "mcmc_step_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_i32, c_i32, c_vp]),
     "propose_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_vp, c_vp, c_vp]),

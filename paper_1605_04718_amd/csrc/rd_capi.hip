@@ -64,7 +64,41 @@ long tune_key(int dev, int n, int prec)
 
 }  // namespace
 
+// Scratch of log_likelihood_batch_noalloc: the queue head (the first 256
+// bytes), then one solve slot per workgroup (predictor history and the low
+// parts of the compensated fields; streamed tiles also their strip arrays).
+// Every device the library runs on holds one copy until the process ends.
+// In host code `scratch` names a host-side stand-in: its device address is
+// taken once per device with hipGetSymbolAddress and used from then on.
+constexpr size_t kNoAllocHeader = 256;
+constexpr size_t kNoAllocSlots = (size_t)64 << 20;  // 64 MiB of solve slots
+static __device__ __align__(256) unsigned char scratch[kNoAllocHeader + kNoAllocSlots];
 
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+
+// This device's address of `scratch` (the device must be current).
+int32_t scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return RD_OK;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(RD_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                    hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return RD_OK;
+}
+
+}  // namespace
 
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
@@ -106,6 +140,7 @@ struct rd_problem {
     int *iters_ws = nullptr;
     int *cost_ws = nullptr;      // [max_batch] per-chain solve cost estimate (-1: none yet)
     int *steps_ws = nullptr;     // [max_batch] IMEX steps each item of a sampler solve completed
+    void *scratch = nullptr;     // this device's address of the no-allocation scratch array
     uint64_t *ctr = nullptr;
     void *gws = nullptr;     // per-workgroup solve slots
     size_t gws_stride = 0;
@@ -214,10 +249,20 @@ hipError_t record_solve_end(rd_problem *p, hipStream_t s, hipEvent_t start)
 // the autotuner times each class on its own).
 // cost (optional, [n]): per-item cost estimates (negative: unknown); a
 // single-class launch then takes its items largest first.
+// Workspace of one solve launch other than the problem's own: the queue
+// head and the per-workgroup slots (single-class launches of a resident or
+// streamed tile only).
+struct SolveWs {
+    unsigned *queue;
+    void *gws;
+    size_t stride;
+    int slots;
+};
+
 int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid_id,
                       const int *need, double *phi, int *status, int *iters, void *u_out,
                       void *v_out, hipStream_t s, int cls = 0, int *steps_out = nullptr,
-                      const int *cost = nullptr)
+                      const int *cost = nullptr, const SolveWs *ws = nullptr)
 {
     if (n == 0)
         return RD_OK;
@@ -254,10 +299,23 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
     a.coop_wait_ticks = p->coop_wait_ticks;
     a.coop_stall_ticks = p->coop_stall_ticks;
     a.coop_timeouts = p->coop_timeouts;
+    if (ws) {
+        a.queue = ws->queue;
+        a.gws = ws->gws;
+        a.gws_stride = ws->stride;
+        a.gws_slots = ws->slots;
+        a.coop = nullptr;
+        a.coop_groups = 0;
+    }
     const TileChoice t = p->tile[g];
     // wgs_per_cu was queried when the tile was chosen: no runtime query may
     // run here, since this is also called while a stream is being captured.
     int wgs = p->n_cu * (mixed ? p->mixed_wpc : p->wgs_per_cu[g]);
+    if (ws) {
+        if (mixed || cost || tile_coop(nn, p->desc.precision, t.cpt))
+            return fail(RD_EUNSUPPORTED, "external workspace: single-class, uncooperative tiles only");
+        wgs = std::min(wgs, ws->slots);
+    }
     // (a cooperative tile sizes its grid from the item count itself)
     if (wgs > n && (mixed || !tile_coop(nn, p->desc.precision, t.cpt)))
         wgs = n;
@@ -287,8 +345,9 @@ int32_t enqueue_solve(rd_problem *p, int n, const double *theta, const int *grid
         HIP_TRY(launch_cost_order(n, need, cost, p->order_ws, s));
         a.order = p->order_ws;
     }
-    hipEvent_t e0;
-    HIP_TRY(record_solve_start(p, s, &e0));
+    hipEvent_t e0 = nullptr;
+    if (!ws)  // (event creation may allocate: an external workspace is never timed)
+        HIP_TRY(record_solve_start(p, s, &e0));
     if (!mixed) {
         HIP_TRY(launch_solve(nn, p->desc.precision, t, a, wgs, s));
     } else if (a.coop_wgs && fused) {
@@ -481,6 +540,10 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
         return fail(RD_EHIP, "no HIP device");
     }
     p->n_cu = prop.multiProcessorCount;
+    if ((err = scratch_address(p->device, &p->scratch)) != RD_OK) {
+        delete p;
+        return err;
+    }
     int max_n = 0;
     for (int g = 0; g < desc->n_grids; ++g) {
         const rd_grid_desc &gd = desc->grids[g];
@@ -686,6 +749,41 @@ extern "C" int32_t log_likelihood_batch(rd_problem *p, int32_t n, const double *
             return fail(RD_EINVAL, "a grid class has no data y");
     return enqueue_solve(p, n, theta, grid_id, nullptr, phi, status, cg_iters, nullptr, nullptr,
                          (hipStream_t)stream);
+}
+
+extern "C" int32_t log_likelihood_batch_noalloc(rd_problem *p, int32_t n, const double *theta,
+                                                double *phi, int32_t *status, int32_t *cg_iters,
+                                                void *stream)
+{
+    int32_t r = check_batch(p, n);
+    if (r != RD_OK)
+        return r;
+    if (n > 0 && (!status || !phi || !theta))
+        return fail(RD_EINVAL, "theta, phi and status are required");
+    if (p->desc.n_grids != 1)
+        return fail(RD_EUNSUPPORTED, "log_likelihood_batch_noalloc takes one grid class");
+    if (!p->grids_host[0].y)
+        return fail(RD_EINVAL, "grid 0 has no data y");
+    const int nn = p->grids_host[0].n;
+    const TileChoice t = p->tile[0];
+    if (tile_coop(nn, p->desc.precision, t.cpt))
+        return fail(RD_EUNSUPPORTED,
+                    "log_likelihood_batch_noalloc: the cooperative %dx%d tile needs the problem's "
+                    "group workspace (select a streamed tile with rd_set_tile)", nn, nn);
+    if (!p->scratch)
+        return fail(RD_EHIP, "no scratch address for device %d", p->device);
+    const size_t stride = (solve_slot_bytes(nn, p->desc.precision, t.cpt) + 255) / 256 * 256;
+    const size_t slots = kNoAllocSlots / stride;
+    if (slots < 1)
+        return fail(RD_EUNSUPPORTED,
+                    "log_likelihood_batch_noalloc: one solve slot (%zu bytes) exceeds the %zu "
+                    "bytes of scratch", stride, kNoAllocSlots);
+    if (n == 0)
+        return RD_OK;
+    SolveWs ws{(unsigned *)p->scratch, (char *)p->scratch + kNoAllocHeader, stride,
+               (int)std::min<size_t>(slots, (size_t)1 << 20)};
+    return enqueue_solve(p, n, theta, nullptr, nullptr, phi, status, cg_iters, nullptr, nullptr,
+                         (hipStream_t)stream, 0, nullptr, nullptr, &ws);
 }
 
 extern "C" int32_t field_misfit_batch(rd_problem *p, int32_t n, const void *u,
