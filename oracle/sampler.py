@@ -39,6 +39,8 @@ PURPOSE_STAGE1 = 2
 PURPOSE_PMH_AUX = 6       # parallel MH: the auxiliary point
 PURPOSE_PMH_PROP = 7      # parallel MH: proposal j from blocks 2j, 2j + 1
 PURPOSE_PMH_RESAMPLE = 8  # parallel MH: uniform of draw n from block n
+PURPOSE_SUB_PROPOSAL = 9  # surrogate chain: normals of substep j >= 1 (blocks 2j, 2j + 1)
+PURPOSE_SUB_ACCEPT = 10   # surrogate chain: uniform of substep j >= 1 (block j)
 
 
 def propose(phi, seed, chain, step, step_sd, free_mask, chol=None):
@@ -185,6 +187,71 @@ def da_step(phi, loglik, loglik_sur, seed, chain, step, lo, hi, step_sd, free_ma
     log_alpha2 = (loglik - ll_prop) - (loglik_sur - sur_prop)
     if math.log(u2) < log_alpha2:
         return prop, ll_prop, sur_prop, True, True, True
+    return (*keep, True, False, True)
+
+
+def rw_move(x, z, step_sd, free_mask, chol=None):
+    """x + s .* z, or x + L z, on the free coordinates (row i of L z summed
+    over j = 0..i in that order)."""
+    y = np.array(x, dtype=np.float64).copy()
+    for i in range(4):
+        if (free_mask >> i) & 1:
+            if chol is not None:
+                dz = 0.0
+                for j in range(i + 1):
+                    dz = dz + float(chol[i][j]) * float(z[j])
+            else:
+                dz = step_sd[i] * z[i]
+            y[i] = y[i] + dz
+    return y
+
+
+def da_chain_step(phi, loglik, loglik_sur, seed, chain, step, m, lo, hi, step_sd, free_mask,
+                  loglik_fn, surrogate_fn, prior=None, chol=None):
+    """Delayed acceptance whose first stage is m Metropolis steps on the
+    surrogate posterior (prior x exp(-Phi~)) from the present state x
+    (Christen and Fox 2005 with the surrogate's own Markov kernel as the
+    proposal, the surrogate transition of Liu, Monte Carlo Strategies in
+    Scientific Computing, 2001).  Substep j proposes z' = z + s .* dz (or
+    z + L dz) from the substep's state z and accepts it iff
+    log U_j < [Phi~(z) - Phi~(z')] + [log pi(z') - log pi(z)]; the end point
+    y of the m substeps is the proposal of the second stage, which accepts
+    iff log U < [Phi(x) - Phi(y)] - [Phi~(x) - Phi~(y)] (the prior ratio
+    cancels).  The surrogate kernel is reversible for the surrogate
+    posterior, which makes the two-stage step reversible for the posterior.
+    When no substep moves, y = x and nothing is solved.
+
+    Random numbers: substep 0 uses the proposal normals (purpose 0) and the
+    first-stage uniform (purpose 2) of the step, so that m = 1 is da_step;
+    substep j >= 1 uses purpose 9 (blocks 2j, 2j + 1) and purpose 10
+    (block j); the second stage purpose 1.
+
+    Returns (phi, loglik, loglik_sur, moved1, accepted, solved): moved1 =
+    the surrogate chain left x (the proposal reaches the second stage)."""
+    z = np.array(phi, dtype=np.float64)
+    lz = loglik_sur
+    moves = 0
+    for j in range(m):
+        if j == 0:
+            dz = normals4(seed, chain, step, PURPOSE_PROPOSAL)
+            u = uniform1(seed, chain, step, PURPOSE_STAGE1)
+        else:
+            dz = normals4_at(seed, chain, step, PURPOSE_SUB_PROPOSAL, 2 * j)
+            u = uniform_at(seed, chain, step, PURPOSE_SUB_ACCEPT, j)
+        prop = rw_move(z, dz, step_sd, free_mask, chol)
+        if not in_support(prop, lo, hi, prior):
+            continue
+        lp = float(surrogate_fn(prop))
+        if math.log(u) < (lz - lp) + log_prior_ratio(z, prop, prior):
+            z, lz = prop, lp
+            moves += 1
+    keep = (np.array(phi, dtype=np.float64), loglik, loglik_sur)
+    if moves == 0:
+        return (*keep, False, False, False)
+    ll_prop = float(loglik_fn(z))
+    u2 = uniform1(seed, chain, step, PURPOSE_ACCEPT)
+    if math.log(u2) < (loglik - ll_prop) - (loglik_sur - lz):
+        return z, ll_prop, lz, True, True, True
     return (*keep, True, False, True)
 
 

@@ -7,7 +7,8 @@ moments, decimal square roots), and the stationary law of delayed
 acceptance on Gaussian toy targets whose posterior is known in closed form.
 Every check is also run on a planted mistake (a dropped 1/2, sigma1 instead
 of sigma1^2, a constant bias correction, the prior ratio in the second
-stage) and must fail there.
+stage, a surrogate chain corrected by the plain Metropolis ratio) and must
+fail there.
 """
 import math
 
@@ -271,3 +272,80 @@ def test_da_with_biased_surrogate_recovers_a_correlated_gaussian():
     emp = np.cov(x.T)
     bound = 4.5 * np.sqrt((cov ** 2 + np.outer(np.diag(cov), np.diag(cov))) / C)
     assert np.all(np.abs(emp - cov) < bound)
+
+
+# --------------------------------------------------------------------------
+# Delayed acceptance with a surrogate chain as the first stage
+
+def _chain_run(phi0, step_fn, S, seed):
+    phis = np.array(phi0, dtype=np.float64)
+    ll = np.array([_lik(p) for p in phis])
+    ls = np.array([_sur(p) for p in phis])
+    moved = acc = 0
+    for s in range(S):
+        for c in range(len(phis)):
+            phis[c], ll[c], ls[c], m1, a, _ = step_fn(phis[c], ll[c], ls[c], seed, c, s)
+            moved += m1
+            acc += a
+    return phis, moved, acc
+
+
+def test_surrogate_chain_with_one_substep_is_the_delayed_acceptance_step():
+    """m = 1 uses the same random numbers as da_step and takes the same
+    decisions: identical paths, bit for bit."""
+    step_sd = np.array([0, 0, 1.4, 0])
+    pa = pb = np.array([0.0, 0.0, 0.3, 0.0])
+    la = lb = _lik(pa)
+    sa = sb = _sur(pa)
+    for s in range(200):
+        pa, la, sa, a1, aa, _ = osamp.da_step(pa, la, sa, 9, 2, s, BOX_LO, BOX_HI, step_sd,
+                                              0b0100, _lik, _sur, prior=_PRIOR)
+        pb, lb, sb, b1, ab, _ = osamp.da_chain_step(pb, lb, sb, 9, 2, s, 1, BOX_LO, BOX_HI,
+                                                    step_sd, 0b0100, _lik, _sur, prior=_PRIOR)
+        assert a1 == b1 and aa == ab
+        assert np.array_equal(pa, pb) and la == lb and sa == sb
+
+
+def _check_chain_posterior(step_fn, C=300, S=40):
+    rng = np.random.default_rng(43)
+    phi0 = np.zeros((C, 4))
+    phi0[:, 2] = rng.normal(1.0, math.sqrt(0.5), C)  # exact posterior draws
+    phis, moved, acc = _chain_run(phi0, step_fn, S, seed=78)
+    x = phis[:, 2]
+    assert 0.2 < acc / (C * S) < 1.0 and moved > acc
+    se = math.sqrt(0.5 / C)
+    assert abs(x.mean() - 1.0) < 4.5 * se, x.mean()
+    assert abs(x.std() - math.sqrt(0.5)) < 4.5 * math.sqrt(0.5) / math.sqrt(2 * C), x.std()
+
+
+def _chain_step(m, prior=_PRIOR):
+    def f(p, l, ls, seed, c, s):
+        return osamp.da_chain_step(p, l, ls, seed, c, s, m, BOX_LO, BOX_HI,
+                                   np.array([0, 0, 1.4, 0]), 0b0100, _lik, _sur, prior=prior)
+    return f
+
+
+def test_surrogate_chain_keeps_the_posterior():
+    """Five substeps on a biased, wider surrogate with a normal prior: the
+    posterior N(1, 1/2) is kept."""
+    _check_chain_posterior(_chain_step(5))
+
+
+def test_surrogate_chain_pin_catches_planted_mistakes():
+    # planted: the second stage takes the plain Metropolis ratio
+    # Phi(x) - Phi(y) on the end point of the surrogate chain, without the
+    # surrogate's [Phi~(x) - Phi~(y)]; passing Phi + Phi~(y) - Phi~(x) as the
+    # misfit of y makes da_chain_step's second stage exactly that
+    def plain_second_stage(p, l, ls, seed, c, s):
+        y, _, ls_y, m1, a, solved = osamp.da_chain_step(
+            p, l, ls, seed, c, s, 5, BOX_LO, BOX_HI, np.array([0, 0, 1.4, 0]), 0b0100,
+            lambda q: _lik(q) + _sur(q) - _sur(p), _sur, prior=_PRIOR)
+        if a:
+            return y, _lik(y), ls_y, m1, a, solved
+        return p, l, ls, m1, a, solved
+
+    with pytest.raises(AssertionError):
+        _check_chain_posterior(plain_second_stage)
+    # planted: the substeps leave out the prior ratio (they target exp(-Phi~) alone)
+    with pytest.raises(AssertionError):
+        _check_chain_posterior(_chain_step(5, prior=None))
