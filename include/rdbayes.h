@@ -190,12 +190,12 @@ int32_t log_likelihood_batch(rd_problem *p, int32_t n, const double *theta,
  * log_likelihood_batch with grid_id = NULL (the same kernels; items are
  * independent, so the launch shape does not change any result), but the
  * solve's scratch (queue head and one workspace slot per workgroup) lives
- * in a file-scope device array of the library, 256 B + 64 MiB, one copy per
+ * in a file-scope device array of the library, 256 B + 96 MiB, one copy per
  * device, held until the process ends, instead of the problem's workspace.
  * The call allocates nothing (no hipMalloc, events or library routines that
  * allocate) and enqueues a fill kernel and the solve kernel on `stream`.
- * The launch uses at most as many workgroups as slots fit in the 64 MiB
- * (256 at 128 x 128 FP32, 51 at 128 x 128 FP64), so it is never wider than
+ * The launch uses at most as many workgroups as slots fit in the 96 MiB
+ * (256 at 128 x 128 FP32, 64 at 128 x 128 FP64), so it is never wider than
  * the scratch; larger batches are served by the persistent queue.
  * Every call on a device shares that device's array: calls that overlap on
  * one device (other streams, other problems, other threads) race and must
@@ -382,6 +382,30 @@ int32_t rd_set_tile(rd_problem *p, int32_t grid, int32_t cpt);
  * with 512 a cooperative launch for those items precedes the mixed launch.
  * Errors: RD_EINVAL (NULL problem, other sizes). */
 int32_t rd_set_mixed_threads(rd_problem *p, int32_t threads);
+
+/* First stage of delayed acceptance (mcmc_step_batch with RD_MODE_DA):
+ * `substeps` Metropolis steps on the surrogate posterior prior x exp(-Phi~)
+ * from the present state x instead of one screened proposal.  Substep j
+ * proposes z' = z + step .* dz (or z + L dz) from the substep state z and
+ * accepts iff log U_j < [Phi~(z) - Phi~(z')] + [log pi(z') - log pi(z)];
+ * the end point y goes to the full solve and the second stage (accept iff
+ * log U < [Phi(x) - Phi(y)] - [Phi~(x) - Phi~(y)]) when some substep moved,
+ * else the step stays at x without a solve.  The surrogate's kernel is
+ * reversible for the surrogate posterior, so the step leaves the posterior
+ * invariant (delayed acceptance of Christen and Fox 2005 with the surrogate
+ * transition as the proposal).  Random numbers: substep 0 uses purposes 0
+ * and 2 (so substeps = 1 is the one-proposal step), substep j >= 1
+ * purpose 9 (blocks 2j, 2j + 1) and 10 (block j).  n_accept1 counts the
+ * steps whose proposal reached the second stage.  1 <= substeps <= 256
+ * (default 1).  Errors: RD_EINVAL. */
+int32_t rd_set_da_substeps(rd_problem *p, int32_t substeps);
+
+/* Number of Metropolis steps held as captured HIP graphs (one per chains
+ * layout, mode and stream; host int32 out).  Every setting that changes
+ * what a step launches (tile, mixed workgroup size, surrogate, substeps,
+ * group-wait hook) drops them, so the next step is captured anew.
+ * Errors: RD_EINVAL. */
+int32_t rd_captured_graphs(const rd_problem *p, int32_t *count);
 
 /* Workgroup size of the launch that serves batches mixing grid classes
  * (host int32 out).  Errors: RD_EINVAL (NULL argument). */

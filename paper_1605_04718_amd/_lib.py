@@ -83,8 +83,10 @@ SYMBOLS = {
     "forward_solve_steady_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                            c_vp]),
     "rd_set_mixed_threads": (c_i32, [c_vp, c_i32]),
+    "rd_set_da_substeps": (c_i32, [c_vp, c_i32]),
     "rd_solver_timing": (c_i32, [c_vp, c_i32, c_dp, ctypes.POINTER(c_i64), c_i32]),
     "rd_mixed_threads": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),
+    "rd_captured_graphs": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),
     "surrogate_set_input_box": (c_i32, [c_vp, c_dp, c_dp]),
     "g1d_init": (c_i32, [ctypes.POINTER(G1dDesc), ctypes.POINTER(c_vp)]),
     "g1d_destroy": (c_i32, [c_vp]),

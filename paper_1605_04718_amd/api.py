@@ -310,6 +310,17 @@ class Problem:
         """Workgroup size (512 or 1024) of the launch for batches mixing classes."""
         check(lib().rd_set_mixed_threads(self.h, int(threads)), "rd_set_mixed_threads")
 
+    def set_da_substeps(self, substeps):
+        """First stage of delayed acceptance: that many Metropolis steps on
+        the surrogate posterior (1: one screened proposal)."""
+        check(lib().rd_set_da_substeps(self.h, int(substeps)), "rd_set_da_substeps")
+
+    def captured_graphs(self):
+        """Metropolis steps currently held as captured HIP graphs."""
+        t = ctypes.c_int32()
+        check(lib().rd_captured_graphs(self.h, ctypes.byref(t)), "rd_captured_graphs")
+        return t.value
+
     def mixed_threads(self):
         """Workgroup size of the launch that serves batches mixing grid classes."""
         t = ctypes.c_int32()

@@ -71,7 +71,7 @@ long tune_key(int dev, int n, int prec)
 // In host code `scratch` names a host-side stand-in: its device address is
 // taken once per device with hipGetSymbolAddress and used from then on.
 constexpr size_t kNoAllocHeader = 256;
-constexpr size_t kNoAllocSlots = (size_t)64 << 20;  // 64 MiB of solve slots
+constexpr size_t kNoAllocSlots = (size_t)96 << 20;  // 96 MiB of solve slots
 static __device__ __align__(256) unsigned char scratch[kNoAllocHeader + kNoAllocSlots];
 
 namespace {
@@ -140,6 +140,12 @@ struct rd_problem {
     int *iters_ws = nullptr;
     int *cost_ws = nullptr;      // [max_batch] per-chain solve cost estimate (-1: none yet)
     int *steps_ws = nullptr;     // [max_batch] IMEX steps each item of a sampler solve completed
+    // delayed acceptance: first-stage substeps on the surrogate (1: one
+    // screened proposal) and the surrogate chain's state
+    int da_substeps = 1;
+    double *sub_phi = nullptr;   // [max_batch][4]
+    double *sub_ll = nullptr;    // [max_batch]
+    int *sub_moves = nullptr;    // [max_batch]
     void *scratch = nullptr;     // this device's address of the no-allocation scratch array
     uint64_t *ctr = nullptr;
     void *gws = nullptr;     // per-workgroup solve slots
@@ -420,6 +426,9 @@ SamplerArgs sampler_args(rd_problem *p, const rd_chains *c)
     a.fail_bits = c->fail_bits;
     a.steps = p->steps_ws;
     a.status = p->status_ws;
+    a.sub_phi = p->sub_phi;
+    a.sub_ll = p->sub_ll;
+    a.sub_moves = p->sub_moves;
     a.trace = c->trace;
     a.trace_rows = c->trace ? c->trace_rows : 0;
     return a;
@@ -432,11 +441,25 @@ int32_t enqueue_mcmc_step(rd_problem *p, const rd_chains *c, int mode, hipStream
     HIP_TRY(launch_propose(a, s));
     if (mode == RD_MODE_PLAIN) {
         HIP_TRY(launch_copy_i32(p->inside, p->need, c->n_chains, s));
-    } else {
+    } else if (p->da_substeps <= 1) {
         int32_t r = surrogate_enqueue_loglik(p->sur, c->n_chains, p->phi_prop, p->ll_sur_prop, s);
         if (r != RD_OK)
             return fail(r, "surrogate evaluation failed: %s", hipGetErrorString(hipGetLastError()));
         HIP_TRY(launch_da_stage1(a, s));
+    } else {
+        // first stage: da_substeps Metropolis steps on the surrogate posterior
+        // (substep 0 starts the chain at the present state and proposes what
+        // launch_propose drew)
+        for (int j = 0; j < p->da_substeps; ++j) {
+            HIP_TRY(launch_sub_propose(a, j, s));
+            int32_t r = surrogate_enqueue_loglik(p->sur, c->n_chains, p->phi_prop,
+                                                 p->ll_sur_prop, s);
+            if (r != RD_OK)
+                return fail(r, "surrogate evaluation failed: %s",
+                            hipGetErrorString(hipGetLastError()));
+            HIP_TRY(launch_sub_accept(a, j, s));
+        }
+        HIP_TRY(launch_sub_finish(a, s));
     }
     // cost_ws keeps, per chain, a decaying maximum of the CG iterations of
     // its solved proposals (-1 before the first): the cost estimate of this
@@ -598,6 +621,9 @@ extern "C" int32_t init_problem(const rd_problem_desc *desc, rd_problem **out)
     p->cost_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
     p->coop_timeouts = (unsigned *)dmalloc(p, 64, &err);
     p->steps_ws = (int *)dmalloc(p, sizeof(int) * B, &err);
+    p->sub_phi = (double *)dmalloc(p, sizeof(double) * 4 * B, &err);
+    p->sub_ll = (double *)dmalloc(p, sizeof(double) * B, &err);
+    p->sub_moves = (int *)dmalloc(p, sizeof(int) * B, &err);
     if (err != RD_OK) {
         destroy_problem(p);
         return err;
@@ -1259,6 +1285,25 @@ extern "C" int32_t rd_set_coop_wait(rd_problem *p, int64_t wait_ticks, int64_t s
     p->coop_wait_ticks = wait_ticks > 0 ? (unsigned long long)wait_ticks : 1000000000ull;
     p->coop_stall_ticks = (unsigned long long)stall_ticks;
     drop_graphs(p);  // captured launches carry the old values
+    return RD_OK;
+}
+
+extern "C" int32_t rd_set_da_substeps(rd_problem *p, int32_t substeps)
+{
+    if (!p)
+        return fail(RD_EINVAL, "problem is NULL");
+    if (substeps < 1 || substeps > 256)
+        return fail(RD_EINVAL, "substeps must be in [1, 256], got %d", substeps);
+    p->da_substeps = substeps;
+    drop_graphs(p);  // captured steps carry the substep count of their capture
+    return RD_OK;
+}
+
+extern "C" int32_t rd_captured_graphs(const rd_problem *p, int32_t *count)
+{
+    if (!p || !count)
+        return fail(RD_EINVAL, "problem and count are required");
+    *count = (int32_t)p->graphs.size();
     return RD_OK;
 }
 

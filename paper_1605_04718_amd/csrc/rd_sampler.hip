@@ -18,6 +18,8 @@ enum : uint32_t {
     kPurposePmhAux = 6,       // parallel MH: the auxiliary point
     kPurposePmhProp = 7,      // parallel MH: proposal j from blocks 2j, 2j + 1
     kPurposePmhResample = 8,  // parallel MH: uniform of draw n from block n
+    kPurposeSubProp = 9,      // surrogate chain: normals of substep j >= 1 (blocks 2j, 2j + 1)
+    kPurposeSubAccept = 10,   // surrogate chain: uniform of substep j >= 1 (block j)
 };
 
 // The four inequalities of eq. (turing) for the activator-depleted kinetics
@@ -328,6 +330,97 @@ __global__ void k_da_stage1(SamplerArgs a)
         a.n_accept1[c] += 1;
 }
 
+// Delayed acceptance whose first stage is m Metropolis steps on the
+// surrogate posterior prior x exp(-Phi~), started at the present state x
+// (the surrogate transition: the surrogate's own reversible kernel as the
+// proposal of Christen and Fox's second stage).  Substep j proposes
+// z' = z + s .* dz (or z + L dz) from the substep state z, with the normals
+// of purpose 0 (j = 0) or purpose 9 (blocks 2j, 2j + 1): the same proposal
+// as k_propose at j = 0, when z = x.
+__global__ void k_sub_propose(SamplerArgs a, int j)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n)
+        return;
+    const uint64_t step = a.ctr[0];
+    double *z = a.sub_phi + 4 * c;
+    if (j == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            z[i] = a.phi[4 * c + i];
+        a.sub_ll[c] = a.loglik_sur[c];
+        a.sub_moves[c] = 0;
+    }
+    const uint32_t purpose = j == 0 ? kPurposeProposal : kPurposeSubProp;
+    const uint32_t block = j == 0 ? 0u : 2u * (uint32_t)j;
+    double dz[4], p[4];
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, purpose, block), dz[0], dz[1]);
+    gauss_pair(stream_block(a.seed, (uint32_t)c, step, purpose, block + 1), dz[2], dz[3]);
+    rw_move(a.cfg, z, dz, p);
+    const double d = exp(p[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        a.phi_prop[4 * c + i] = p[i];
+    if (a.theta_prop) {
+        a.theta_prop[4 * c + 0] = p[0];
+        a.theta_prop[4 * c + 1] = p[1];
+        a.theta_prop[4 * c + 2] = exp(p[2]);
+        a.theta_prop[4 * c + 3] = d;
+    }
+    a.inside[c] = in_support(a.cfg, p, d) ? 1 : 0;
+}
+
+// Substep j's test: log U < [Phi~(z) - Phi~(z')] + [log pi(z') - log pi(z)]
+// with U from purpose 2 (j = 0, the first-stage uniform of k_da_stage1) or
+// purpose 10 (block j).
+__global__ void k_sub_accept(SamplerArgs a, int j)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n || !a.inside[c])
+        return;
+    const uint64_t step = a.ctr[0];
+    const U32x4 w = j == 0 ? stream_block(a.seed, (uint32_t)c, step, kPurposeStage1, 0)
+                           : stream_block(a.seed, (uint32_t)c, step, kPurposeSubAccept, (uint32_t)j);
+    const double u = unit_open(w.x, w.y);
+    double *z = a.sub_phi + 4 * c;
+    const double *prop = a.phi_prop + 4 * c;
+    const double lpr = a.cfg.any_normal ? prior_quad(a.cfg, z) - prior_quad(a.cfg, prop) : 0.0;
+    if (log(u) < (a.sub_ll[c] - a.loglik_sur_prop[c]) + lpr) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            z[i] = prop[i];
+        a.sub_ll[c] = a.loglik_sur_prop[c];
+        a.sub_moves[c] += 1;
+    }
+}
+
+// The end point y of the surrogate chain becomes the proposal of the second
+// stage (solved) when some substep moved; otherwise y = x and nothing is
+// solved.  n_accept1 counts the proposals that reach the second stage.
+__global__ void k_sub_finish(SamplerArgs a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n)
+        return;
+    const bool moved = a.sub_moves[c] > 0;
+    a.need[c] = moved ? 1 : 0;
+    if (!moved)
+        return;
+    const double *z = a.sub_phi + 4 * c;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        a.phi_prop[4 * c + i] = z[i];
+    if (a.theta_prop) {
+        a.theta_prop[4 * c + 0] = z[0];
+        a.theta_prop[4 * c + 1] = z[1];
+        a.theta_prop[4 * c + 2] = exp(z[2]);
+        a.theta_prop[4 * c + 3] = exp(z[3]);
+    }
+    a.loglik_sur_prop[c] = a.sub_ll[c];
+    if (a.n_accept1)
+        a.n_accept1[c] += 1;
+}
+
 // Second stage: log U2 < [Phi(phi) - Phi(phi')] - [Phi~(phi) - Phi~(phi')].
 __global__ void k_da_stage2(SamplerArgs a)
 {
@@ -438,6 +531,24 @@ hipError_t launch_accept(const SamplerArgs &a, hipStream_t s)
 hipError_t launch_da_stage1(const SamplerArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_da_stage1, chain_blocks(a.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_propose(const SamplerArgs &a, int j, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_propose, chain_blocks(a.n), dim3(256), 0, s, a, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_accept(const SamplerArgs &a, int j, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_accept, chain_blocks(a.n), dim3(256), 0, s, a, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_finish(const SamplerArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_finish, chain_blocks(a.n), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -202,23 +202,30 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 // one strip array fewer in VGPRs.  hi is not changed (the caller folds d
 // in).  r and q are scratch.  Returns RD status bits.
 //
-// H (global, the previous step's increment, or null): with `pred`, CG starts
-// from one minimal-residual step along it, d0 = w H with
-// w = (r0, A H) / (A H, A H), which can only lower the residual.  When the
-// trajectory is smooth in time this removes the part of r0 that the last
-// step predicts.  The system and the stopping test are unchanged:
-// |r| <= rtol |b| on the recursively updated residual.
+// H1, H2 (global): the increments of the last two steps.  npred = 1: CG
+// starts from one minimal-residual step along H1, d0 = w H1 with
+// w = (r0, A H1) / (A H1, A H1), which can only lower the residual.
+// npred = 2: d0 = w1 H1 + w2 H2 with the Galerkin condition
+// (H_i, r0 - A d0) = 0, i.e. the 2 x 2 system (H_i, A H_j) w = (H_i, r0): the
+// start vector of least error in the A-norm over span{H1, H2}, which CG's own
+// iterates also minimise (a minimal-residual pair cancels smoothness the
+// energy norm keeps; measured on the CPU, it saves fewer iterations).  When
+// the trajectory is smooth in time the pair extrapolates the increment to
+// second order.  npred = 0: d0 = 0.  The system and the stopping test are
+// unchanged: |r| <= rtol |b| on the recursively updated residual.  `quiet`
+// returns whether r0 itself met the tolerance (the field did not move).
 //
 // kFuse (resident FP32): on entry the other species' field is still in
 // registers (Sreg) and the LDS stash behind S is free.  The residuals of hi
 // and of lo are then formed in one pass, lo staged in the stash, and Sreg
 // is parked in the stash afterwards (S reads it from there on).
-template <int N, int R, int U, int NW, bool kLds, int kSp, bool kFuse = false, typename Real,
-          class Arr, class SArr>
+template <int N, int R, int U, int NW, bool kLds, int kSp, bool kFuse = false, bool kPred2 = false,
+          typename Real, class Arr, class SArr>
 __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Real inv_dt, Real c,
                         Real src, Real dl, Real gam, double rtol2, int maxit, Real *P,
-                        const Real *lo, const Real *H, bool pred, double *red, const Geo<N, R> &g,
-                        int &it_acc, const Arr *Sreg = nullptr, Real *stash = nullptr)
+                        const Real *lo, const Real *H1, const Real *H2, int npred, double *red,
+                        const Geo<N, R> &g, int &it_acc, int &quiet, const Arr *Sreg = nullptr,
+                        Real *stash = nullptr)
 {
     constexpr bool comp = Compensated<Real>::on;
     static_assert(!kFuse || (comp && kLds), "the fused set-up is for resident FP32 solves");
@@ -310,10 +317,86 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
     }
     }
     bool rr_pending = false;
-    if (H && pred) {
+    if (kPred2 && npred == 2) {
+        // Gram entries (H_i, A H_j) and (H_i, r0) from two stencil sweeps;
+        // then d0 = w1 H1 + w2 H2 goes to P and one more sweep forms A d0.
+        // No stencil result is kept across sweeps (register pressure).
         if constexpr (!kFuse)
             __syncthreads();  // every stencil read of P is done
-        copy_to_lds<N, R, U, kLds>(H + g.off(), P, g);
+        copy_to_lds<N, R, U, kLds>(H1 + g.off(), P, g);
+        __syncthreads();
+        const Real *h2 = H2 + g.off();
+        double g11 = 0.0, g12 = 0.0, b1 = 0.0;
+        sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
+            Real w = c * t + sigma_at(k) * own;  // (A H1) at the cell
+            RD_PIN(w);
+            const double wd = (double)w;
+            g11 += (double)own * wd;
+            g12 += (double)h2[k * N] * wd;        // (H2, A H1) = (H1, A H2)
+            b1 += (double)own * (double)r[k];
+            RD_PIN(g11);
+            RD_PIN(g12);
+            RD_PIN(b1);
+        });
+        __syncthreads();  // every stencil read of H1 is done
+        copy_to_lds<N, R, U, kLds>(h2, P, g);
+        __syncthreads();
+        double g22 = 0.0, b2 = 0.0;
+        sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
+            Real w = c * t + sigma_at(k) * own;  // (A H2) at the cell
+            RD_PIN(w);
+            g22 += (double)own * (double)w;
+            b2 += (double)own * (double)r[k];
+            RD_PIN(g22);
+            RD_PIN(b2);
+        });
+        double v7[7] = {bb, rr, g11, g12, g22, b1, b2};
+        block_sum_n<NW>(v7, red + Slots<NW>::setup);
+        bb = v7[0];
+        rr = v7[1];
+        g11 = v7[2];
+        g12 = v7[3];
+        g22 = v7[4];
+        b1 = v7[5];
+        b2 = v7[6];
+        quiet = !(rr > rtol2 * bb);
+        double w1 = 0.0, w2 = 0.0;
+        const double det = g11 * g22 - g12 * g12;
+        if (g11 > 0.0 && g22 > 0.0 && finite(det) && det > 1e-12 * g11 * g22 && finite(b1) &&
+            finite(b2)) {
+            w1 = (b1 * g22 - b2 * g12) / det;
+            w2 = (b2 * g11 - b1 * g12) / det;
+        } else if (g11 > 0.0 && finite(b1)) {
+            w1 = b1 / g11;  // the pair is (nearly) dependent: H1 alone
+        }
+        const Real W1 = uniform((Real)w1), W2 = uniform((Real)w2);
+        // d0 = w1 H1 + w2 H2 (own cells; the reduction barrier ended the
+        // stencil reads of H2), then r0 - A d0 from its stencil
+        const Real *h1 = H1 + g.off();
+#pragma unroll U
+        for (int k = 0; k < R; ++k) {
+            Real dk = W1 * h1[k * N];
+            dk = dk + W2 * P[g.idx(k)];
+            RD_PIN(dk);
+            d[k] = dk;
+            P[g.idx(k)] = dk;
+            RD_GROUP_FENCE(k)
+        }
+        __syncthreads();
+        sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
+            Real w = c * t + sigma_at(k) * own;  // (A d0) at the cell
+            RD_PIN(w);
+            r[k] = r[k] - w;
+        });
+        // every stencil read of P is done before the threads overwrite
+        // their own cells with the residual below
+        __syncthreads();
+        // |r0 - A d0|^2 is summed from the updated r in the first CG sweep
+        rr_pending = true;
+    } else if (npred == 1) {
+        if constexpr (!kFuse)
+            __syncthreads();  // every stencil read of P is done
+        copy_to_lds<N, R, U, kLds>(H1 + g.off(), P, g);
         __syncthreads();
         double rw = 0.0, ww = 0.0;
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
@@ -331,6 +414,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         rr = v4[1];
         rw = v4[2];
         ww = v4[3];
+        quiet = !(rr > rtol2 * bb);
         const Real w = uniform((Real)((ww > 0.0 && finite(rw)) ? rw / ww : 0.0));
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
@@ -345,6 +429,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         rr_pending = true;
     } else {
         block_sum2<NW>(bb, rr, red + Slots<NW>::setup);
+        quiet = !(rr > rtol2 * bb);
 #pragma unroll U
         for (int k = 0; k < R; ++k)
             d[k] = Real(0);
@@ -527,11 +612,14 @@ __device__ __forceinline__ void store_increment(Arr &d, Real *H, const Geo<N, R>
 }
 
 // Per-workgroup global slot of the solve: the low parts of u and v (FP32),
-// the last increments of u and v (predictor), then (streamed variant only)
-// the strip arrays and p.
+// the increments of u and v of the last two steps (predictor history, two
+// buffers per species that alternate by step parity), then (streamed
+// variant only) the strip arrays and p.
 template <typename Real>
 struct SlotLayout {
-    static constexpr int lo_u = 0, lo_v = 1, h_u = 2, h_v = 3, arrays = 4;
+    static constexpr int lo_u = 0, lo_v = 1, arrays = 6;
+    // history buffer k (0 or 1) of species sp (0 u, 1 v)
+    static constexpr int hist(int sp, int k) { return 2 + sp + 2 * k; }
 };
 
 // All IMEX steps of one item (Sec. 3.1.1):
@@ -544,7 +632,12 @@ struct SlotLayout {
 // (v^n during the u solve, u^n during the v solve), so that a solve keeps
 // four strip arrays in VGPRs.  Streamed variant: all arrays are global and
 // `stash` is null.  `slot` is the item's global slot (SlotLayout).
-template <int N, int R, int U, int NW, bool kLds, typename Real, class Arr>
+//
+// kPred2: the CG start vector uses the increments of the last two steps
+// (cg_solve, npred = 2); otherwise the last one only.  Kernels that inline
+// several grid classes keep the one-increment start (its fewer live values
+// keep their register spills down).
+template <int N, int R, int U, int NW, bool kLds, typename Real, bool kPred2, class Arr>
 //
 // steady_tt > 0 (Sec. 3.1.2): stop after the first step whose discrete time
 // derivative has an L2 norm over the unit square below the threshold,
@@ -560,8 +653,6 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
     constexpr bool comp = Compensated<Real>::on;
     Real *const lo_u = comp ? slot + L::lo_u * N * N : nullptr;
     Real *const lo_v = comp ? slot + L::lo_v * N * N : nullptr;
-    Real *const h_u = slot + L::h_u * N * N;
-    Real *const h_v = slot + L::h_v * N * N;
     // Per-item and per-step scalars are wave-uniform; keeping them in SGPRs
     // leaves the VGPRs to the strip arrays.
     const Real inv_dt = uniform((Real)(1.0 / dt));
@@ -576,31 +667,40 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
     double rho_m2 = 1.0;
     int st = 0;
     // The predictor pays off only while the field moves: a species whose
-    // last solve needed no CG iteration skips it (its residual was already
-    // below the tolerance without it).
-    int last_u = 0, last_v = 0;
+    // last residual met the tolerance before any correction skips it.  The
+    // start vector from two increments costs two more stencil sweeps than
+    // the one from the last increment, so it is taken only after a solve
+    // that needed at least two CG iterations.
+    int quiet_u = 0, quiet_v = 0, last_u = 0, last_v = 0;
     for (int s = 0; s < n_steps; ++s, rho_m2 = uniform(rho_m2 * decay)) {
         const Real cu = uniform((Real)(rho_m2 * n2));
         const Real cv = uniform((Real)(th[3] * rho_m2 * n2));
-        const bool pred_u = s > 0 && last_u > 0;
-        const bool pred_v = s > 0 && last_v > 0;
+        // history: buffer (s & 1) holds the increment of step s - 2 and
+        // receives this step's; buffer (s & 1) ^ 1 holds step s - 1's
+        const int kn = s & 1;
+        Real *const hu_new = slot + L::hist(0, kn) * N * N;
+        Real *const hv_new = slot + L::hist(1, kn) * N * N;
+        const Real *const hu_last = slot + L::hist(0, kn ^ 1) * N * N;
+        const Real *const hv_last = slot + L::hist(1, kn ^ 1) * N * N;
+        const int npred_u = (s == 0 || quiet_u) ? 0 : (s == 1 || !kPred2 || last_u < 2) ? 1 : 2;
+        const int npred_v = (s == 0 || quiet_v) ? 0 : (s == 1 || !kPred2 || last_v < 2) ? 1 : 2;
         const int itu0 = itu, itv0 = itv;
         if constexpr (kLds && comp) {
             // FP32: each solve parks the other field itself, after its fused
             // residual pass has used the stash for the low part
             LdsArr<Real, N> sv{stash + g.idx(0)};
-            st = cg_solve<N, R, U, NW, kLds, 0, true>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam,
-                                                      rtol2, maxit, P, lo_u, h_u, pred_u, red, g,
-                                                      itu, &xv, stash);
+            st = cg_solve<N, R, U, NW, kLds, 0, true, kPred2>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam,
+                                                      rtol2, maxit, P, lo_u, hu_last, hu_new,
+                                                      npred_u, red, g, itu, quiet_u, &xv, stash);
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 xv[k] = sv[k];
             if (st)
                 break;
-            store_increment<N, R, U>(d, h_u, g);
-            st = cg_solve<N, R, U, NW, kLds, 1, true>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam,
-                                                      rtol2, maxit, P, lo_v, h_v, pred_v, red, g,
-                                                      itv, &xu, stash);
+            store_increment<N, R, U>(d, hu_new, g);
+            st = cg_solve<N, R, U, NW, kLds, 1, true, kPred2>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam,
+                                                      rtol2, maxit, P, lo_v, hv_last, hv_new,
+                                                      npred_v, red, g, itv, quiet_v, &xu, stash);
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 xu[k] = sv[k];
@@ -609,8 +709,9 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 sv[k] = xv[k];
-            st = cg_solve<N, R, U, NW, kLds, 0>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
-                                                maxit, P, lo_u, h_u, pred_u, red, g, itu);
+            st = cg_solve<N, R, U, NW, kLds, 0, false, kPred2>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
+                                                maxit, P, lo_u, hu_last, hu_new, npred_u, red, g,
+                                                itu, quiet_u);
 #pragma unroll U
             for (int k = 0; k < R; ++k) {
                 xv[k] = sv[k];
@@ -619,34 +720,37 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
             }
             if (st)
                 break;
-            store_increment<N, R, U>(d, h_u, g);
-            st = cg_solve<N, R, U, NW, kLds, 1>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
-                                                maxit, P, lo_v, h_v, pred_v, red, g, itv);
+            store_increment<N, R, U>(d, hu_new, g);
+            st = cg_solve<N, R, U, NW, kLds, 1, false, kPred2>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
+                                                maxit, P, lo_v, hv_last, hv_new, npred_v, red, g,
+                                                itv, quiet_v);
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 xu[k] = sv[k];
         } else {
-            st = cg_solve<N, R, U, NW, kLds, 0>(xu, xv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
-                                                maxit, P, lo_u, h_u, pred_u, red, g, itu);
+            st = cg_solve<N, R, U, NW, kLds, 0, false, kPred2>(xu, xv, r, q, d, inv_dt, cu, src_u, dl, gam, rtol2,
+                                                maxit, P, lo_u, hu_last, hu_new, npred_u, red, g,
+                                                itu, quiet_u);
             if (st)
                 break;
-            store_increment<N, R, U>(d, h_u, g);
-            st = cg_solve<N, R, U, NW, kLds, 1>(xv, xu, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
-                                                maxit, P, lo_v, h_v, pred_v, red, g, itv);
+            store_increment<N, R, U>(d, hu_new, g);
+            st = cg_solve<N, R, U, NW, kLds, 1, false, kPred2>(xv, xu, r, q, d, inv_dt, cv, src_v, dl, gam, rtol2,
+                                                maxit, P, lo_v, hv_last, hv_new, npred_v, red, g,
+                                                itv, quiet_v);
         }
         if (st)
             break;
         steps = s + 1;
         if (steady_tt > 0.0) {
             double acc = 0.0;
-            fold<N, R, U, false>(xv, d, lo_v, h_v, g, &acc);
-            fold<N, R, U, true>(xu, d, lo_u, h_u, g, &acc);
+            fold<N, R, U, false>(xv, d, lo_v, hv_new, g, &acc);
+            fold<N, R, U, true>(xu, d, lo_u, hu_new, g, &acc);
             const double thr = steady_tt * (double)N;
             if (block_sum<NW>(acc, red + Slots<NW>::misfit) < thr * thr)
                 return st;
         } else {
-            fold<N, R, U, false>(xv, d, lo_v, h_v, g);
-            fold<N, R, U, true>(xu, d, lo_u, h_u, g);
+            fold<N, R, U, false>(xv, d, lo_v, hv_new, g);
+            fold<N, R, U, true>(xu, d, lo_u, hu_new, g);
         }
         last_u = uniform(itu - itu0);
         last_v = uniform(itv - itv0);
@@ -758,7 +862,7 @@ __device__ __forceinline__ int item_grid(const SolveArgs &a, int c)
 }
 
 // One item, resident variant: P and stash are LDS arrays of at least N*N.
-template <int N, int R, typename Real>
+template <int N, int R, typename Real, bool kPred2 = false>
 __device__ __forceinline__ void solve_item_resident(const SolveArgs &a, int c, const GridDev &gd,
                                                     Real *P, Real *stash, double *red, Real *slot)
 {
@@ -769,7 +873,8 @@ __device__ __forceinline__ void solve_item_resident(const SolveArgs &a, int c, c
     RegArr<Real, R> xu, xv, r, q, d;
     load_initial<N, R, R>(gd, xu, xv, slot, g);
     int itu = 0, itv = 0, steps = 0;
-    const int st = integrate<N, R, R, NW, true>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps, a.rtol2,
+    const int st = integrate<N, R, R, NW, true, Real, kPred2>(xu, xv, r, q, d, th, gd, a.dt,
+                                                              a.n_steps, a.rtol2,
                                                 a.maxit, P, stash, slot, red, g, itu, itv,
                                                 a.steady_tt, steps);
     finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red, steps);
@@ -777,7 +882,7 @@ __device__ __forceinline__ void solve_item_resident(const SolveArgs &a, int c, c
 
 // One item, streamed variant: the strip arrays and p follow the SlotLayout
 // arrays in the workgroup's global slot.
-template <int N, int R, typename Real>
+template <int N, int R, typename Real, bool kPred2 = false>
 __device__ __forceinline__ void solve_item_streamed(const SolveArgs &a, int c, const GridDev &gd,
                                                     double *red, Real *slot)
 {
@@ -794,7 +899,8 @@ __device__ __forceinline__ void solve_item_streamed(const SolveArgs &a, int c, c
                           a.theta[4 * c + 3]};
     load_initial<N, R, U>(gd, xu, xv, slot, g);
     int itu = 0, itv = 0, steps = 0;
-    const int st = integrate<N, R, U, NW, false>(xu, xv, r, q, d, th, gd, a.dt, a.n_steps, a.rtol2,
+    const int st = integrate<N, R, U, NW, false, Real, kPred2>(xu, xv, r, q, d, th, gd, a.dt,
+                                                               a.n_steps, a.rtol2,
                                                  a.maxit, P, (Real *)nullptr, slot, red, g, itu,
                                                  itv, a.steady_tt, steps);
     finish_item<N, R, Real>(a, gd, c, xu, xv, st, itu, itv, slot, g, red, steps);
@@ -815,7 +921,7 @@ __global__ __launch_bounds__(N *N / R) void k_solve_resident(SolveArgs a)
         if (!a.need || uniform(a.need[c])) {
             const int gid = item_grid(a, c);
             if (gid >= 0)
-                solve_item_resident<N, R, Real>(a, c, a.grids[gid], P, stash, red, slot);
+                solve_item_resident<N, R, Real, true>(a, c, a.grids[gid], P, stash, red, slot);
         }
     }
 }
@@ -833,7 +939,7 @@ __global__ __launch_bounds__(N *N / R) void k_solve_streamed(SolveArgs a)
         if (!a.need || uniform(a.need[c])) {
             const int gid = item_grid(a, c);
             if (gid >= 0)
-                solve_item_streamed<N, R, Real>(a, c, a.grids[gid], red, slot);
+                solve_item_streamed<N, R, Real, true>(a, c, a.grids[gid], red, slot);
         }
     }
 }
@@ -1967,7 +2073,9 @@ size_t solve_slot_bytes(int n, int precision, int cpt)
 {
     if (tile_kind(n, precision, cpt) == kCoop)  // one member's strip: 4 arrays
         return (size_t)4 * kCoopStrip * kCoopN * sizeof(float);
-    const size_t arrays = tile_kind(n, precision, cpt) == kStreamed ? 10 : 4;
+    // SlotLayout: low parts and two increments per species (6 arrays), and
+    // for streamed tiles the strip arrays and p after them (6 more)
+    const size_t arrays = tile_kind(n, precision, cpt) == kStreamed ? 12 : 6;
     return arrays * n * n * (precision ? sizeof(double) : sizeof(float));
 }
 
@@ -2021,7 +2129,7 @@ bool mixed_supported(int n, int precision, int threads)
 
 size_t mixed_slot_bytes(int n, int precision, int threads)
 {
-    const size_t arrays = mixed_resident(n, precision, threads) ? 4 : 10;
+    const size_t arrays = mixed_resident(n, precision, threads) ? 6 : 12;
     return arrays * n * n * (precision ? sizeof(double) : sizeof(float));
 }
 

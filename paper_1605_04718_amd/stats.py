@@ -111,6 +111,8 @@ def mcse_quantile(x: np.ndarray, p: float) -> float:
     x = np.asarray(x, dtype=np.float64)
     s = _split(x)
     ess = ess_raw((s <= np.quantile(s, p)).astype(np.float64))
+    if not np.isfinite(ess) or ess <= 0:
+        return float("nan")
     from scipy import stats as st
     a = st.beta.ppf(0.1586553, ess * p + 1, ess * (1 - p) + 1)
     b = st.beta.ppf(0.8413447, ess * p + 1, ess * (1 - p) + 1)
