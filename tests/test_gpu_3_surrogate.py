@@ -251,3 +251,141 @@ def test_full_size_network_gradients_and_three_adam_steps_match_oracle():
         for (aW, ab), (wW, wb) in zip(after, want_after):
             assert np.abs(aW - wW).max() < 2e-6 and np.abs(ab - wb).max() < 2e-6, t
     p.close()
+
+
+def _oracle_sur(p, y, mean, sd, sigma1, out_side=8):
+    params = host_params(p)
+    ybar = omlp.block_mean(y, out_side).reshape(-1)
+
+    def sur(q):
+        return float(omlp.surrogate_misfit(params, q, LO, HI, mean, sd, ybar, sigma1)[0])
+    return sur
+
+
+def test_surrogate_chain_with_constant_surrogate_replays_with_the_oracle():
+    """Delayed acceptance with a four-substep surrogate chain, a constant
+    Phi~ (zero output layer) and a normal prior on ln gamma: each substep's
+    decision then rests on the prior ratio and the support alone (FP64 on
+    both sides), so the GPU trace must follow the oracle's surrogate-chain
+    step exactly, the oracle taking its own FP64 misfits of the proposals."""
+    import torch
+    from paper_1605_04718_amd.api import DA, ChainState, Grid, Problem
+    need_gpu()
+    n, steps, S, C, m = 32, 6, 4, 16, 4
+    u0, v0 = inputs.initial_fields(n, 0.1, 0.9)
+    uo, _, _, _ = oracle.forward_solve(THETA_TRUE, u0, v0, TAU, steps, rtol=1e-12)
+    y, sigma = inputs.noisy_data(uo, 0.01)
+    step = np.array([0.004, 0.004, 0.05, 0.01])
+    prior = osamp.Prior(kinds=(0, 0, 1, 0), mean=(0, 0, math.log(200.0), 0), sd=(1, 1, 0.1, 1))
+    p = Problem([Grid(n=n, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, steps, 1e-12, precision=1,
+                lo=LO, hi=HI, step=step, max_batch=64, prior_kind=prior.kinds,
+                prior_mean=prior.mean, prior_sd=prior.sd)
+    p.surrogate_create(128, 2, 8, seed=5)
+    params = p.surrogate_params(0)
+    params[-1] = (torch.zeros_like(params[-1][0]), torch.zeros_like(params[-1][1]))
+    p.surrogate_params(1, params)
+    p.surrogate_set_scaling(torch.ones(64, device="cuda"), torch.ones(64, device="cuda"), 0.1)
+    p.set_da_substeps(m)
+    phi0 = np.tile(inputs.to_sampling(THETA_TRUE)[0], (C, 1))
+    phi0[:, 1] += np.linspace(-0.01, 0.01, C)
+    ll0, _, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"))
+    ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0.clone(), seed=29,
+                           trace_steps=S, da=True)
+    ch.loglik_sur = p.surrogate_loglik(torch.tensor(phi0, device="cuda"))
+    sur0 = float(ch.loglik_sur[0].item())
+    p.mcmc_step(ch, S, mode=DA)
+    torch.cuda.synchronize()
+    trace = ch.trace.cpu().numpy()
+    acc1 = ch.n_accept1.cpu().numpy()
+
+    def ll(q):
+        return float(oracle.loglik_batch(inputs.to_natural(np.atleast_2d(q)), u0, v0, y, sigma,
+                                         TAU, steps, rtol=1e-12)[0][0])
+
+    ll0 = ll0.cpu().numpy()
+    replayed = 0
+    for c in range(C):
+        cur, l, ls = phi0[c].copy(), float(ll0[c]), sur0
+        moved = 0
+        for s in range(S):
+            cur, l, ls, m1, _, _ = osamp.da_chain_step(cur, l, ls, 29, c, s, m, LO, HI, step,
+                                                       0b1111, ll, lambda q: sur0, prior=prior)
+            moved += m1
+            assert np.allclose(trace[s, c], cur, rtol=1e-12, atol=1e-13), (c, s, trace[s, c], cur)
+        assert acc1[c] == moved
+        replayed += 1
+    assert replayed == C
+    assert acc1.sum() > 0
+    p.close()
+
+
+def test_surrogate_chain_decisions_match_the_oracle():
+    """A trained-looking (random-weight) surrogate and three substeps: each
+    chain's surrogate chain is replayed with the oracle network evaluated in
+    FP64 from the GPU's weights; chains where any decision lies within the
+    BF16 error of Phi~ of its threshold are not compared."""
+    import torch
+    from paper_1605_04718_amd.api import DA, ChainState
+    need_gpu()
+    step = np.array([0.01, 0.01, 0.02, 0.02])
+    m = 3
+    p, u0, v0, y, sigma = small_problem(step=step, precision=1, steps=6)
+    mean, sd, sigma1 = np.ones(64), np.full(64, 0.05), 0.2
+    p.surrogate_set_scaling(torch.tensor(mean, dtype=torch.float32, device="cuda"),
+                            torch.tensor(sd, dtype=torch.float32, device="cuda"), sigma1)
+    p.set_da_substeps(m)
+    C = 64
+    phi0 = np.tile(inputs.to_sampling(THETA_TRUE)[0], (C, 1))
+    phi0[:, 0] += np.linspace(-0.02, 0.02, C)
+    ll0, _, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"))
+    ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0.clone(), seed=31, da=True)
+    ch.loglik_sur = p.surrogate_loglik(torch.tensor(phi0, device="cuda"))
+    lls0 = ch.loglik_sur.cpu().numpy().copy()
+    p.mcmc_step(ch, 1, mode=DA)
+    torch.cuda.synchronize()
+    sur = _oracle_sur(p, y, mean, sd, sigma1)
+
+    def ll(q):
+        return float(oracle.loglik_batch(inputs.to_natural(np.atleast_2d(q)), u0, v0, y, sigma,
+                                         TAU, 6, rtol=1e-12)[0][0])
+
+    got_phi = ch.phi.cpu().numpy()
+    acc1 = ch.n_accept1.cpu().numpy()
+    acc = ch.n_accept.cpu().numpy()
+    ll0 = ll0.cpu().numpy()
+    compared = 0
+    for c in range(C):
+        # the surrogate chain with margins: skip the chain if any decision is close
+        z, lz, close, moves = phi0[c].copy(), sur(phi0[c]), False, 0
+        for j in range(m):
+            if j == 0:
+                dz = oracle.normals4(31, c, 0, osamp.PURPOSE_PROPOSAL)
+                u = oracle.uniform1(31, c, 0, osamp.PURPOSE_STAGE1)
+            else:
+                dz = oracle.normals4_at(31, c, 0, osamp.PURPOSE_SUB_PROPOSAL, 2 * j)
+                u = oracle.uniform_at(31, c, 0, osamp.PURPOSE_SUB_ACCEPT, j)
+            prop = osamp.rw_move(z, dz, step, 0b1111)
+            if not osamp.in_box(prop, LO, HI):
+                continue
+            lp = sur(prop)
+            tol = 0.05 * (abs(lz) + abs(lp) + 1.0)
+            if abs(math.log(u) - (lz - lp)) < tol:
+                close = True
+                break
+            if math.log(u) < lz - lp:
+                z, lz, moves = prop, lp, moves + 1
+        if close:
+            continue
+        if moves:
+            la2 = (ll0[c] - ll(z)) - (sur(phi0[c]) - lz)
+            if abs(math.log(oracle.uniform1(31, c, 0, osamp.PURPOSE_ACCEPT)) - la2) < \
+                    0.05 * (abs(sur(phi0[c])) + abs(lz) + 1.0):
+                continue
+        res = osamp.da_chain_step(phi0[c], float(ll0[c]), float(lls0[c]), 31, c, 0, m, LO, HI,
+                                  step, 0b1111, ll, sur)
+        assert bool(acc1[c]) == res[3], c
+        assert bool(acc[c]) == res[4], c
+        assert np.allclose(got_phi[c], res[0], rtol=1e-12, atol=1e-13), c
+        compared += 1
+    assert compared > C // 3
+    p.close()

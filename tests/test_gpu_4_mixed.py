@@ -190,3 +190,50 @@ def test_mixed_autotune_and_graph_step():
     assert torch.equal(runs[0].trace, runs[1].trace)
     assert torch.equal(runs[0].loglik, runs[1].loglik)
     p.close()
+
+
+def test_changing_the_launch_shape_drops_captured_steps():
+    """A Metropolis step captured as a graph with 1024-thread workgroups is
+    not replayed after the workgroup size (or a tile) changes: the setters
+    drop every captured step, the next step on the stream is captured anew,
+    and chains stepped through both shapes agree bit for bit with chains
+    stepped directly with the same shapes."""
+    import torch
+    from paper_1605_04718_amd.api import ChainState
+    need_gpu()
+    steps = 3
+    p, fields = classes_problem(steps, data=True)
+    ids = torch.tensor(batch_ids(12, seed=13), device="cuda")
+    phi0 = np.tile(inputs.to_sampling(THETA_TRUE)[0], (12, 1))
+    phi0[:, 1] += np.linspace(-0.01, 0.01, 12)
+    ll0, st0, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"),
+                                   grid_id=ids)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0.clone(), seed=5,
+                           trace_steps=4, grid_id=ids)
+    p.set_mixed_threads(1024)
+    assert p.captured_graphs() == 0
+    with torch.cuda.stream(side):
+        p.mcmc_step(ch, 2)       # the first step runs directly, the second is captured
+    side.synchronize()
+    assert p.captured_graphs() == 1
+    p.set_mixed_threads(512)
+    assert p.captured_graphs() == 0
+    with torch.cuda.stream(side):
+        p.mcmc_step(ch, 2)
+    side.synchronize()
+    assert p.captured_graphs() == 1
+    p.set_tile(0, 16)
+    assert p.captured_graphs() == 0
+    # the same steps launched directly (null stream) with the same shapes
+    ref = ChainState.create(torch.tensor(phi0, device="cuda"), ll0.clone(), seed=5,
+                            trace_steps=4, grid_id=ids)
+    p.set_mixed_threads(1024)
+    p.mcmc_step(ref, 2)
+    p.set_mixed_threads(512)
+    p.mcmc_step(ref, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(ch.trace, ref.trace)
+    assert torch.equal(ch.loglik, ref.loglik)
+    p.close()

@@ -75,3 +75,144 @@ def test_full_size_fp64_matches_oracle():
         print(f"full-size FP64 item {k}: rel L2 u {eu:.3e} v {ev:.3e} (tolerance {tol:.3e})")
         assert eu < tol and ev < tol
     p.close()
+
+
+CLASSES_GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                            "full_size_classes.npz")
+P256_GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "precision_256.npz")
+
+
+def r17_tolerance(amplification, eps, cg_sensitivity):
+    """FP32 field tolerance of a full-horizon item: max(1e-5, 4 A eps, 4 S)."""
+    return max(1e-5, 4 * float(amplification) * float(eps), 4 * float(cg_sensitivity))
+
+
+@pytest.mark.parametrize("threads", [1024, 512])
+def test_full_size_every_class_in_one_uneven_launch(threads):
+    """One item of every class of the uneven workload (64^2, 128^2, 256^2;
+    stationary and growing rho = exp(0.01 t)) to T = 2 (8000 steps) inside a
+    48-item batch of all classes: 1024 threads is the fused launch (groups of
+    four workgroups solve the 256^2 items, then join the queue of the
+    others), 512 a cooperative launch followed by the mixed launch.  Stored
+    FP64 oracle fields, tolerance per item as for the 128^2 workload."""
+    import torch
+    from paper_1605_04718_amd.api import Grid, Problem
+    need_gpu()
+    g = np.load(CLASSES_GOLD, allow_pickle=False)
+    ns, growth, thetas_g = g["n"], g["growth"], g["theta"]
+    steps, rate = int(g["steps"]), float(g["rate"])
+    assert abs(float(g["tau"]) - TAU) < 1e-15
+    grids = []
+    for n, gr in zip(ns, growth):
+        u0, v0 = inputs.initial_fields(int(n), THETA_TRUE[0], THETA_TRUE[1])
+        grids.append(Grid(n=int(n), u0=u0, v0=v0, growth=int(gr),
+                          growth_rate=rate if gr else 0.0))
+    m = 48
+    ids = np.arange(m, dtype=np.int32) % len(grids)
+    thetas = theta_batch(m, seed=57)
+    slots = [5 * len(grids) + k for k in range(len(grids))]   # item k of class k
+    for k, c in enumerate(slots):
+        assert ids[c] == k
+        thetas[c] = thetas_g[k]
+    p = Problem(grids, TAU, steps, float(g["rtol_fp32"]), cg_maxit=1600, max_batch=m)
+    p.set_mixed_threads(threads)
+    print(f"uneven launch ({threads} threads): {m} items, {steps} steps", flush=True)
+    u, v, st, _ = p.forward_solve(torch.tensor(thetas, device="cuda"),
+                                  grid_id=torch.tensor(ids, device="cuda"))
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    for k, c in enumerate(slots):
+        n = int(ns[k])
+        tol = r17_tolerance(g[f"amplification_{k}"], g["eps"], g[f"cg_sensitivity_{k}"])
+        assert st[c] == 0 and int(g[f"status_{k}"]) == 0
+        eu = rel_l2(u[c, :n * n].double().cpu().numpy(), g[f"u_{k}"].reshape(-1))
+        ev = rel_l2(v[c, :n * n].double().cpu().numpy(), g[f"v_{k}"].reshape(-1))
+        print(f"class item {k} (n={n}, growth={int(growth[k])}): rel L2 u {eu:.3e} v {ev:.3e} "
+              f"(tolerance {tol:.3e})")
+        assert eu < tol and ev < tol, (k, eu, ev, tol)
+    assert int((st != 0).sum()) < m // 4
+    assert p.check_solves() == 0
+    p.close()
+
+
+def test_fp32_256_against_the_oracle_16_prior_draws():
+    """The FP32 path at 256^2 (cooperative tile, CG rtol 1e-7) to T = 2 for
+    16 prior draws against stored FP64 oracle fields (rtol 1e-10): every
+    draw both sides solve agrees within its tolerance, max(1e-5, 4 A 6e-8,
+    4 S), from the oracle's own amplification A of a relative 6e-8 change of
+    the initial fields and its CG-tolerance sensitivity S."""
+    import torch
+    from paper_1605_04718_amd.api import Grid, Problem
+    need_gpu()
+    g = np.load(P256_GOLD, allow_pickle=False)
+    n, steps, m = int(g["n"]), int(g["steps"]), len(g["theta"])
+    u0, v0 = inputs.initial_fields(n, THETA_TRUE[0], THETA_TRUE[1])
+    p = Problem([Grid(n=n, u0=u0, v0=v0)], TAU, steps, float(g["rtol_fp32"]), cg_maxit=1600,
+                max_batch=m)
+    print(f"256^2 FP32: {m} prior draws, {steps} steps", flush=True)
+    u, v, st, _ = p.forward_solve(torch.tensor(g["theta"], device="cuda"))
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    both = 0
+    for k in range(m):
+        if int(g["status"][k]) != 0:
+            continue
+        if st[k] != 0:
+            # a failure in FP32 only is allowed near the stability limit, not in general
+            print(f"draw {k}: FP32 status {st[k]}, oracle solved")
+            continue
+        both += 1
+        tol = r17_tolerance(g["amplification"][k], g["eps"], g["cg_sensitivity"][k])
+        eu = rel_l2(u[k].double().cpu().numpy(), g["u"][k])
+        ev = rel_l2(v[k].double().cpu().numpy(), g["v"][k])
+        print(f"draw {k}: rel L2 u {eu:.3e} v {ev:.3e}, amplification "
+              f"{float(g['amplification'][k]):.3g}, tolerance {tol:.3e}")
+        assert eu < tol and ev < tol, (k, eu, ev, tol)
+    assert both >= m - 2
+    p.close()
+
+
+LOGLIK_GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "loglik_64.npz")
+
+
+def test_misfit_at_64_posterior_points_against_the_oracle():
+    """The FP32 misfit Phi (128^2, T = 2, CG rtol 1e-9, all 64 items in one
+    launch) at 64 parameter vectors spread like the posterior, against the
+    FP64 oracle's Phi at rtol 1e-9 and 1e-12 (tests/golden/loglik_64.npz).
+    Bound per point: the oracle's own change between rtol 1e-9 and 1e-12,
+    twice (the two sides stop at different iterates), plus what a relative
+    field error e = 1e-5 can move Phi = |u - y|^2 / (2 sigma^2) by:
+    |r| e |u| / sigma^2 + (e |u|)^2 / (2 sigma^2), with |r| = sigma sqrt(2 Phi)
+    and |u| <= |y| + |r| (Cauchy-Schwarz)."""
+    import torch
+    from paper_1605_04718_amd.api import Grid, Problem
+    need_gpu()
+    g = np.load(LOGLIK_GOLD, allow_pickle=False)
+    n, steps = int(g["n"]), int(g["steps"])
+    sigma = float(g["sigma"])
+    ref, o9 = g["phi_1e-12"], g["phi_1e-09"]
+    assert (g["status_1e-12"] == 0).all() and (g["status_1e-09"] == 0).all()
+    u0, v0 = inputs.initial_fields(n, THETA_TRUE[0], THETA_TRUE[1])
+    th = torch.tensor(inputs.to_natural(g["phi_sampling"]), dtype=torch.float64, device="cuda")
+    p = Problem([Grid(n=n, u0=u0, v0=v0, y=g["y"], sigma=sigma)], TAU, steps, 1e-9,
+                cg_maxit=2000, max_batch=len(th))
+    print(f"misfit at {len(th)} posterior points, {n}^2, {steps} steps", flush=True)
+    phi, st, _ = p.log_likelihood(th)
+    torch.cuda.synchronize()
+    phi, st = phi.cpu().numpy(), st.cpu().numpy()
+    p.close()
+    assert (st == 0).all()
+    ynorm = float(np.linalg.norm(g["y"]))
+    e = 1e-5
+    worst = 0.0
+    for k in range(len(th)):
+        r = sigma * np.sqrt(2.0 * ref[k])
+        un = ynorm + r
+        bound = 2 * abs(o9[k] - ref[k]) + r * e * un / sigma**2 + (e * un)**2 / (2 * sigma**2)
+        d = abs(phi[k] - ref[k])
+        worst = max(worst, d / bound)
+        assert d < bound, (k, phi[k], ref[k], bound)
+    d = phi - ref
+    print(f"|dPhi| max {np.abs(d).max():.3g}, about the mean {np.abs(d - d.mean()).max():.3g}, "
+          f"worst fraction of the bound {worst:.3f}")
