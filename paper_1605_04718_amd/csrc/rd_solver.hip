@@ -1171,7 +1171,13 @@ __device__ __forceinline__ double coop_load(const double *p)
 // and one poll per member, no counter.  The change is below 2^-44 relative,
 // far under the rounding error of the FP64 sums themselves, and every
 // member sums the same tagged values in the same order.  Exchanges are
-// double buffered by sequence parity; a buffer's stale tag is two behind.
+// double buffered by sequence parity, and every exchange rewrites all four
+// slots of its member (unused ones carry zero), so a slot's stale tag is
+// always exactly two behind.  (Were only the M slots in use rewritten, a
+// slot that a long run of one-value exchanges leaves alone would hold the
+// tag of an exchange 256 k sequence numbers back, which the 8-bit tag
+// cannot tell from the present one: the poll would take the old value, and
+// the exchange would stop being a barrier.)
 __device__ __forceinline__ double with_tag(double v, unsigned tag)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -1199,22 +1205,26 @@ __device__ void coop_exchange(double (&v)[M], CoopCtx &x)
     const unsigned tag = x.seq & 0xFFu;
     double *buf = x.partial(x.seq);
     const int t = threadIdx.x;
-    if (t < kCoopG * M) {
-        const int mm = t / M, j = t % M;  // lane t: value j of member mm
-        double mine = v[0];
+    // The store and the polls are separate blocks, store first: as the
+    // two sides of one branch they could run in either order within the
+    // wave, and a wave that polls before it stores waits for members that
+    // do the same.
+    if (t < 4) {  // this member's four slots, value t (zero past M)
+        double mine = 0.0;
 #pragma unroll
-        for (int q = 1; q < M; ++q)
-            if (j == q)
+        for (int q = 0; q < M; ++q)
+            if (t == q)
                 mine = v[q];
-        double got = with_tag(mine, tag);
-        // The store and the polls are separate blocks, store first: as the
-        // two sides of one branch they could run in either order within
-        // the wave, and a wave that polls before it stores waits for
-        // members that do the same.
-        if (mm == x.m)
-            coop_store(buf + lane_off(x.m * 4 + j), got);
-        asm volatile("" ::: "memory");
-        if (mm != x.m && !*x.fail) {
+        const double pub = with_tag(mine, tag);
+        coop_store(buf + lane_off(x.m * 4 + t), pub);
+        if (t < M)
+            x.gather[x.m * M + t] = pub;
+    }
+    asm volatile("" ::: "memory");
+    if (t < kCoopG * M && t / M != x.m) {
+        const int mm = t / M, j = t % M;  // lane t: value j of member mm
+        double got = 0.0;
+        if (!*x.fail) {
             got = coop_load(buf + lane_off(mm * 4 + j));
             if (tag_of(got) != tag) {
                 const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
@@ -1270,19 +1280,23 @@ __device__ void coop_sum(double (&v)[M], double *red, CoopCtx &x)
     x.seq += 1;
     const unsigned tag = x.seq & 0xFFu;
     double *buf = x.partial(x.seq);
-    if (t < kCoopG * M) {
-        const int mm = t / M, j = t % M;  // lane t: value j of member mm
-        double got = 0.0;
-        if (mm == x.m) {
-            double sum = 0.0;
+    if (t < 4) {  // lanes 0..3 publish this member's four slots (zero past M)
+        double sum = 0.0;
+        if (t < M) {
 #pragma unroll
             for (int w = 0; w < NW; ++w)
-                sum += red[j * NW + w];
-            got = with_tag(sum, tag);
-            coop_store(buf + lane_off(x.m * 4 + j), got);
+                sum += red[t * NW + w];
         }
-        asm volatile("" ::: "memory");  // the store is issued before any poll
-        if (mm != x.m && !*x.fail) {
+        const double pub = with_tag(sum, tag);
+        coop_store(buf + lane_off(x.m * 4 + t), pub);
+        if (t < M)
+            x.gather[x.m * M + t] = pub;
+    }
+    asm volatile("" ::: "memory");  // the store is issued before any poll
+    if (t < kCoopG * M && t / M != x.m) {
+        const int mm = t / M, j = t % M;  // lane t: value j of member mm
+        double got = 0.0;
+        if (!*x.fail) {
             got = coop_load(buf + lane_off(mm * 4 + j));
             if (tag_of(got) != tag) {
                 const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();

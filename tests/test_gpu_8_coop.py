@@ -93,6 +93,34 @@ def test_coop_256_more_items_than_groups():
     p.close()
 
 
+def test_coop_256_long_cg_runs_give_identical_bits_in_every_group():
+    """Regression test for the group exchange: 32 copies of one stiff
+    parameter vector (d = 30.5, gamma = 336: tens of CG iterations per step,
+    so long runs of one-value exchanges) solved twice at rtol 1e-9.  Every
+    group sums the same values in the same order, so all 64 results must be
+    the same bits, every item must solve, and no group may give up a wait.
+    A poll that took a stale partial sum (a slot whose 8-bit tag aliased an
+    exchange 256 sequence numbers back) broke exactly this: the members of a
+    group then diverged, giving wrong fields or a group time-out."""
+    import torch
+    need_gpu()
+    steps, m = 2000, 32
+    theta = np.tile([[0.0089, 0.979, 335.7, 30.5]], (m, 1))
+    p, _, _ = make_problem(256, steps, precision=0, rtol=1e-9, maxit=4000, max_batch=m)
+    p.set_tile(0, COOP_CPT)
+    print(f"coop 256 stiff copies: {m} items, {steps} steps, twice", flush=True)
+    u1, v1, st1, it1 = run(p, theta)
+    u2, v2, st2, it2 = run(p, theta)
+    assert np.all(st1 == 0) and np.all(st2 == 0), (st1, st2)
+    assert p.check_solves() == 0
+    assert it1[0, 1] > 20 * steps  # the long-CG regime this test is for
+    for u, v, it in ((u1, v1, it1), (u2, v2, it2)):
+        assert np.array_equal(u, np.broadcast_to(u1[0], u.shape))
+        assert np.array_equal(v, np.broadcast_to(v1[0], v.shape))
+        assert np.array_equal(it, np.broadcast_to(it1[0], it.shape))
+    p.close()
+
+
 def test_set_tile_rejects_unsupported():
     from paper_1605_04718_amd._lib import RDError
     need_gpu()
