@@ -56,7 +56,8 @@ enum {
     RD_EHIP = -2,         /* a HIP runtime call failed */
     RD_ENOMEM = -3,       /* device allocation failed */
     RD_EUNSUPPORTED = -4, /* valid request this build does not implement */
-    RD_ETIMEOUT = -5      /* rd_check_solves: a cooperative group wait gave up */
+    RD_ETIMEOUT = -5,     /* rd_check_solves: a cooperative group wait gave up */
+    RD_EIO = -6           /* rd_chains_save / rd_chains_load: file error */
 };
 
 /* Per-item status bits. */
@@ -259,6 +260,31 @@ typedef struct {
  * without a surrogate). */
 int32_t mcmc_step_batch(rd_problem *p, rd_chains *chains, int32_t n_steps, int32_t mode,
                         void *stream);
+
+/* Checkpoint and resume of chains (Sec. 2: chains are long, and a run that
+ * stops can continue).  The state of a chain is its present point, Phi (and
+ * Phi~ under delayed acceptance) there, its counters, and the host fields
+ * seed and step; the random numbers of step s depend only on (chain, seed,
+ * s), so a chain loaded from a file continues exactly as the saved one
+ * would have.  The trace is output, not state, and is neither saved nor
+ * restored (trace_step0 and trace_rows are left as they are).
+ * rd_chains_save copies every non-NULL array of *chains to the host on
+ * `stream`, waits for it and writes `path`: a 48-byte header (magic
+ * "RDCHAINS", version 1, n_chains, seed, a mask of the arrays present,
+ * step) followed by those arrays in the order phi, loglik, loglik_sur,
+ * grid_id, n_accept, n_accept1, n_solves, cg_iters, imex_steps, fail_bits,
+ * n_chains rows each, host byte order.
+ * rd_chains_load reads such a file into *chains (same n_chains): every
+ * non-NULL array of *chains except grid_id must be in the file and is
+ * overwritten; arrays the file has and *chains does not are skipped;
+ * grid_id, an input, is compared with the file's and never written; seed
+ * and step are set from the file.  Synchronous on `stream`; the surrogate
+ * and the problem are not part of the file (resume DA chains with the same
+ * surrogate).  Errors: RD_EINVAL (NULL or inconsistent arguments, not a
+ * chain file, other n_chains, a missing array, another grid_id), RD_EIO
+ * (open, short read or write), RD_EHIP. */
+int32_t rd_chains_save(const rd_chains *chains, const char *path, void *stream);
+int32_t rd_chains_load(rd_chains *chains, const char *path, void *stream);
 
 /* The two halves of one plain step, for samplers on an external Phi (the
  * non-intrusive use of Sec. 2, and toy targets in tests):

@@ -13,7 +13,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librdbayes.so")
 
-RD_OK, RD_EINVAL, RD_EHIP, RD_ENOMEM, RD_EUNSUPPORTED, RD_ETIMEOUT = 0, -1, -2, -3, -4, -5
+RD_OK, RD_EINVAL, RD_EHIP, RD_ENOMEM, RD_EUNSUPPORTED, RD_ETIMEOUT, RD_EIO = (
+    0, -1, -2, -3, -4, -5, -6)
 ST_NOT_CONVERGED, ST_BREAKDOWN, ST_NONFINITE, ST_OUT_OF_PRIOR = 1, 2, 4, 8
 ST_BAD_GRID, ST_NOT_STEADY, ST_GROUP_TIMEOUT = 16, 32, 64
 PRECISION_FP32, PRECISION_FP64 = 0, 1
@@ -94,6 +95,8 @@ SYMBOLS = {
     "g1d_log_likelihood_batch": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "g1d_mcmc_step_batch": (c_i32, [c_vp, ctypes.POINTER(Chains), c_i32, c_vp]),
     "rd_check_solves": (c_i32, [c_vp, ctypes.POINTER(c_i64), c_i32]),
+    "rd_chains_save": (c_i32, [ctypes.POINTER(Chains), ctypes.c_char_p, c_vp]),
+    "rd_chains_load": (c_i32, [ctypes.POINTER(Chains), ctypes.c_char_p, c_vp]),
     "rd_set_coop_wait": (c_i32, [c_vp, c_i64, c_i64]),
     "rd_status_string": (ctypes.c_char_p, [c_i32]),
     "rd_last_error": (ctypes.c_char_p, []),

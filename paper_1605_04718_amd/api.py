@@ -7,6 +7,7 @@ step of the method.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -481,3 +482,18 @@ class ChainState:
         c.imex_steps = _ptr(self.imex_steps)
         c.fail_bits = _ptr(self.fail_bits)
         return c
+
+    def save(self, path, stream=None):
+        """Write the chain state to `path` (rd_chains_save)."""
+        c = self.struct()
+        check(lib().rd_chains_save(ctypes.byref(c), os.fsencode(path), _stream(stream)),
+              "rd_chains_save")
+
+    def load(self, path, stream=None):
+        """Overwrite this state (same number of chains) from `path`
+        (rd_chains_load); seed and step come from the file."""
+        c = self.struct()
+        check(lib().rd_chains_load(ctypes.byref(c), os.fsencode(path), _stream(stream)),
+              "rd_chains_load")
+        self.seed = int(c.seed)
+        self.step = int(c.step)

@@ -1351,6 +1351,7 @@ extern "C" const char *rd_status_string(int32_t s)
     case RD_ENOMEM: return "out of device memory";
     case RD_EUNSUPPORTED: return "unsupported configuration";
     case RD_ETIMEOUT: return "a cooperative group wait gave up";
+    case RD_EIO: return "file error";
     case RD_ST_NOT_CONVERGED: return "CG not converged";
     case RD_ST_BREAKDOWN: return "CG breakdown (operator not positive definite)";
     case RD_ST_NONFINITE: return "non-finite value";
@@ -1492,5 +1493,162 @@ extern "C" int32_t surrogate_params(rd_problem *p, int32_t layer, float *w, floa
     HIP_TRY(surrogate_copy_params(p->sur, layer, w, b, dir, (hipStream_t)stream));
     if (dir == 1)
         drop_graphs(p);
+    return RD_OK;
+}
+
+// ---- chain state to and from a file ---------------------------------------
+// Layout (little-endian, as the host writes it): a 48-byte header, then the
+// arrays the header's mask names, in the order of kChainArrays, each
+// n_chains x width elements of elem bytes.
+namespace {
+
+constexpr char kChainMagic[8] = {'R', 'D', 'C', 'H', 'A', 'I', 'N', 'S'};
+constexpr uint32_t kChainVersion = 1;
+
+struct ChainFileHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t n_chains;
+    uint32_t seed;
+    uint32_t mask;  // bit k: array k of kChainArrays follows
+    uint64_t step;
+    uint64_t reserved[2];
+};
+static_assert(sizeof(ChainFileHeader) == 48, "chain file header is 48 bytes");
+
+struct ChainArray {
+    const char *name;
+    size_t elem, width;
+};
+// the order of the arrays in the file
+constexpr ChainArray kChainArrays[] = {
+    {"phi", 8, 4},        {"loglik", 8, 1},   {"loglik_sur", 8, 1}, {"grid_id", 4, 1},
+    {"n_accept", 8, 1},   {"n_accept1", 8, 1}, {"n_solves", 8, 1},  {"cg_iters", 8, 2},
+    {"imex_steps", 8, 1}, {"fail_bits", 8, 8},
+};
+constexpr int kNChainArrays = (int)(sizeof(kChainArrays) / sizeof(kChainArrays[0]));
+
+// Device address of array k of the chains (NULL where the caller has none).
+const void *chain_array(const rd_chains *c, int k)
+{
+    switch (k) {
+    case 0: return c->phi;
+    case 1: return c->loglik;
+    case 2: return c->loglik_sur;
+    case 3: return c->grid_id;
+    case 4: return c->n_accept;
+    case 5: return c->n_accept1;
+    case 6: return c->n_solves;
+    case 7: return c->cg_iters;
+    case 8: return c->imex_steps;
+    case 9: return c->fail_bits;
+    default: return nullptr;
+    }
+}
+
+struct File {
+    FILE *f = nullptr;
+    ~File()
+    {
+        if (f)
+            fclose(f);
+    }
+};
+
+}  // namespace
+
+extern "C" int32_t rd_chains_save(const rd_chains *c, const char *path, void *stream)
+{
+    if (!c || !path)
+        return fail(RD_EINVAL, "rd_chains_save: chains and path are required");
+    if (c->n_chains < 0 || !c->phi || !c->loglik)
+        return fail(RD_EINVAL, "rd_chains_save: n_chains >= 0, phi and loglik are required");
+    const hipStream_t s = (hipStream_t)stream;
+    ChainFileHeader h{};
+    memcpy(h.magic, kChainMagic, sizeof h.magic);
+    h.version = kChainVersion;
+    h.n_chains = c->n_chains;
+    h.seed = c->seed;
+    h.step = c->step;
+    std::vector<std::vector<unsigned char>> host(kNChainArrays);
+    for (int k = 0; k < kNChainArrays; ++k) {
+        const void *d = chain_array(c, k);
+        if (!d)
+            continue;
+        h.mask |= 1u << k;
+        host[k].resize((size_t)c->n_chains * kChainArrays[k].elem * kChainArrays[k].width);
+        if (!host[k].empty())
+            HIP_TRY(hipMemcpyAsync(host[k].data(), d, host[k].size(), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    File out;
+    out.f = fopen(path, "wb");
+    if (!out.f)
+        return fail(RD_EIO, "rd_chains_save: cannot open %s for writing", path);
+    bool ok = fwrite(&h, sizeof h, 1, out.f) == 1;
+    for (int k = 0; k < kNChainArrays && ok; ++k)
+        if (!host[k].empty())
+            ok = fwrite(host[k].data(), 1, host[k].size(), out.f) == host[k].size();
+    ok = (fclose(out.f) == 0) && ok;
+    out.f = nullptr;
+    if (!ok)
+        return fail(RD_EIO, "rd_chains_save: write to %s failed", path);
+    return RD_OK;
+}
+
+extern "C" int32_t rd_chains_load(rd_chains *c, const char *path, void *stream)
+{
+    if (!c || !path)
+        return fail(RD_EINVAL, "rd_chains_load: chains and path are required");
+    if (c->n_chains < 0 || !c->phi || !c->loglik)
+        return fail(RD_EINVAL, "rd_chains_load: n_chains >= 0, phi and loglik are required");
+    File in;
+    in.f = fopen(path, "rb");
+    if (!in.f)
+        return fail(RD_EIO, "rd_chains_load: cannot open %s", path);
+    ChainFileHeader h{};
+    if (fread(&h, sizeof h, 1, in.f) != 1)
+        return fail(RD_EIO, "rd_chains_load: %s is shorter than the header", path);
+    if (memcmp(h.magic, kChainMagic, sizeof h.magic) != 0 || h.version != kChainVersion)
+        return fail(RD_EINVAL, "rd_chains_load: %s is not a version-%u chain file", path,
+                    kChainVersion);
+    if (h.n_chains != c->n_chains)
+        return fail(RD_EINVAL, "rd_chains_load: the file holds %d chains, the state %d",
+                    h.n_chains, c->n_chains);
+    if (h.mask >> kNChainArrays)
+        return fail(RD_EINVAL, "rd_chains_load: unknown arrays in %s", path);
+    std::vector<std::vector<unsigned char>> host(kNChainArrays);
+    for (int k = 0; k < kNChainArrays; ++k) {
+        if (!(h.mask >> k & 1u))
+            continue;
+        host[k].resize((size_t)h.n_chains * kChainArrays[k].elem * kChainArrays[k].width);
+        if (fread(host[k].data(), 1, host[k].size(), in.f) != host[k].size())
+            return fail(RD_EIO, "rd_chains_load: %s ends inside array %s", path,
+                        kChainArrays[k].name);
+    }
+    if (fgetc(in.f) != EOF)
+        return fail(RD_EINVAL, "rd_chains_load: %s has bytes after its last array", path);
+    for (int k = 0; k < kNChainArrays; ++k)
+        if (chain_array(c, k) && k != 3 && !(h.mask >> k & 1u))
+            return fail(RD_EINVAL, "rd_chains_load: the state has %s, the file does not",
+                        kChainArrays[k].name);
+    const hipStream_t s = (hipStream_t)stream;
+    if (c->grid_id && (h.mask >> 3 & 1u) && c->n_chains > 0) {
+        // grid classes are an input of the caller: check, never overwrite
+        std::vector<unsigned char> g(host[3].size());
+        HIP_TRY(hipMemcpyAsync(g.data(), c->grid_id, g.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (memcmp(g.data(), host[3].data(), g.size()) != 0)
+            return fail(RD_EINVAL, "rd_chains_load: the chains' grid_id differs from the file's");
+    }
+    for (int k = 0; k < kNChainArrays; ++k) {
+        void *d = const_cast<void *>(chain_array(c, k));
+        if (k == 3 || !d || host[k].empty())
+            continue;
+        HIP_TRY(hipMemcpyAsync(d, host[k].data(), host[k].size(), hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    c->seed = h.seed;
+    c->step = h.step;
     return RD_OK;
 }
