@@ -110,12 +110,20 @@ __device__ __forceinline__ double wave_sum_last_lane(double v)
     return v;
 }
 
+// Index of this wave in its workgroup, read once into a scalar register at
+// the start of a solve and handed to the reductions: recomputed from the
+// thread index inside a hot loop it needs a vector register, which the
+// register allocator of the large kernels then spills and reloads.
+__device__ __forceinline__ int wave_index()
+{
+    return uniform((int)(threadIdx.x / kWave));
+}
+
 template <int kWaves>
-__device__ __forceinline__ double block_sum(double v, double *slot)
+__device__ __forceinline__ double block_sum(double v, double *slot, int wid)
 {
     v = wave_sum_last_lane(v);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
     if (lane == kLastLane)
         slot[wid] = v;
     __syncthreads();
@@ -127,12 +135,18 @@ __device__ __forceinline__ double block_sum(double v, double *slot)
 }
 
 template <int kWaves>
+__device__ __forceinline__ double block_sum(double v, double *slot)
+{
+    return block_sum<kWaves>(v, slot, wave_index());
+}
+
+template <int kWaves>
 __device__ __forceinline__ void block_sum2(double &a, double &b, double *slot)
 {
     a = wave_sum_last_lane(a);
     b = wave_sum_last_lane(b);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    const int wid = wave_index();
     if (lane == kLastLane) {
         slot[wid] = a;
         slot[kWaves + wid] = b;
@@ -149,13 +163,12 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *slot)
 }
 
 template <int kWaves, int M>
-__device__ __forceinline__ void block_sum_n(double (&v)[M], double *slot)
+__device__ __forceinline__ void block_sum_n(double (&v)[M], double *slot, int wid)
 {
 #pragma unroll
     for (int m = 0; m < M; ++m)
         v[m] = wave_sum_last_lane(v[m]);
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
     if (lane == kLastLane) {
 #pragma unroll
         for (int m = 0; m < M; ++m)
@@ -170,6 +183,12 @@ __device__ __forceinline__ void block_sum_n(double (&v)[M], double *slot)
             s += slot[m * kWaves + w];
         v[m] = uniform(s);
     }
+}
+
+template <int kWaves, int M>
+__device__ __forceinline__ void block_sum_n(double (&v)[M], double *slot)
+{
+    block_sum_n<kWaves>(v, slot, wave_index());
 }
 
 __device__ __forceinline__ bool finite(double x)

@@ -36,12 +36,14 @@ namespace rd {
 template <int N, int R>
 struct Geo {
     int i, j0, iw, ie;
+    int wid;  // this wave's index in the workgroup (scalar)
     __device__ Geo()
     {
         i = threadIdx.x % N;
         j0 = (threadIdx.x / N) * R;
         iw = i > 0 ? i - 1 : i;      // mirror ghost at x = 0
         ie = i < N - 1 ? i + 1 : i;  // mirror ghost at x = 1
+        wid = wave_index();
     }
     __device__ int idx(int k) const { return (j0 + k) * N + i; }
     // Own-cell offset for global-memory accesses, made opaque at each use:
@@ -117,6 +119,32 @@ __device__ __forceinline__ void sweep(const Real *P, const Geo<N, R> &g, F &&f)
     }
 }
 
+// As sweep(), but f(k, p_c, s) gets the plain sum of the four neighbours
+// (mirror ghosts give p_c), so that A p = (sigma + 4c) p - c s: three
+// additions per cell instead of seven.  For the CG iteration on a step
+// increment only: there the rounding of the sum form stays below the other
+// FP32 roundings of the iteration (an FP32 emulation of the increment solves
+// reaches the same true residual with the same iteration counts), while the
+// residual of the field itself keeps the exact difference form.
+template <int N, int R, int U, typename Real, typename F>
+__device__ __forceinline__ void sweep_nsum(const Real *P, const Geo<N, R> &g, F &&f)
+{
+    Real cur = P[g.j0 * N + g.i];
+    Real south = (g.j0 > 0) ? P[(g.j0 - 1) * N + g.i] : cur;
+#pragma unroll U
+    for (int k = 0; k < R; ++k) {
+        const int j = g.j0 + k;
+        const Real north = (k + 1 < R || j + 1 < N) ? P[(j + 1) * N + g.i] : cur;
+        const Real west = P[j * N + g.iw];
+        const Real east = P[j * N + g.ie];
+        const Real sn = (west + east) + (south + north);
+        f(k, cur, sn);
+        south = cur;
+        cur = north;
+        RD_GROUP_FENCE(k)
+    }
+}
+
 // sweep() over two arrays with the same layout at once: f(k, p_c, t(p),
 // q_c, t(q)).
 template <int N, int R, int U, typename Real, typename F>
@@ -137,6 +165,41 @@ __device__ __forceinline__ void sweep_pair(const Real *P, const Real *Q, const G
                         ((qcur - qsouth) + (qcur - qnorth));
         f(k, cur, t, qcur, qt);
         south = cur;
+        cur = north;
+        qsouth = qcur;
+        qcur = qnorth;
+        RD_GROUP_FENCE(k)
+    }
+}
+
+// sweep_pair() with the first array's differences formed and summed in FP64:
+// f(k, p_c, t64(p), q_c, t(q)).  The differences of FP32 values are exact
+// in FP64, so t64 carries no rounding error to speak of; the residual of a
+// compensated field needs it (the FP32 sum of the four differences, scaled
+// by c, rounds at about 2^-24 of the diffusion term, which lies above
+// rtol |b| for rtol 1e-9).
+template <int N, int R, int U, typename F>
+__device__ __forceinline__ void sweep_pair64(const float *P, const float *Q, const Geo<N, R> &g,
+                                             F &&f)
+{
+    float cur = P[g.j0 * N + g.i], qcur = Q[g.j0 * N + g.i];
+    double cur64 = cur;
+    double south64 = (g.j0 > 0) ? (double)P[(g.j0 - 1) * N + g.i] : cur64;
+    float qsouth = (g.j0 > 0) ? Q[(g.j0 - 1) * N + g.i] : qcur;
+#pragma unroll U
+    for (int k = 0; k < R; ++k) {
+        const int j = g.j0 + k;
+        const bool in = k + 1 < R || j + 1 < N;
+        const float north = in ? P[(j + 1) * N + g.i] : cur;
+        const float qnorth = in ? Q[(j + 1) * N + g.i] : qcur;
+        const double north64 = north;
+        const double t64 = ((cur64 - (double)P[j * N + g.iw]) + (cur64 - (double)P[j * N + g.ie])) +
+                           ((cur64 - south64) + (cur64 - north64));
+        const float qt = ((qcur - Q[j * N + g.iw]) + (qcur - Q[j * N + g.ie])) +
+                         ((qcur - qsouth) + (qcur - qnorth));
+        f(k, cur, t64, qcur, qt);
+        south64 = cur64;
+        cur64 = north64;
         cur = north;
         qsouth = qcur;
         qcur = qnorth;
@@ -225,7 +288,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
                         Real src, Real dl, Real gam, double rtol2, int maxit, Real *P,
                         const Real *lo, const Real *H1, const Real *H2, int npred, double *red,
                         const Geo<N, R> &g, int &it_acc, int &quiet, const Arr *Sreg = nullptr,
-                        Real *stash = nullptr)
+                        Real *stash = nullptr, const Real *Slo = nullptr)
 {
     constexpr bool comp = Compensated<Real>::on;
     static_assert(!kFuse || (comp && kLds), "the fused set-up is for resident FP32 solves");
@@ -244,15 +307,17 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         else
             return s0 + gam * (S[k] * S[k]);
     };
+    // sigma + 4c, the diagonal of the neighbour-sum form
+    const Real s04 = uniform(s0 + Real(4) * c);
+    auto sigma4_at = [&](int k) -> Real {
+        if constexpr (kSp == 0)
+            return s04 - gam * (hi[k] * S[k]);
+        else
+            return s04 + gam * (S[k] * S[k]);
+    };
     double bb = 0.0, rr = 0.0;
     if constexpr (kFuse) {
         const Arr &Sr = *Sreg;
-        auto e_reg = [&](int k) -> Real {
-            if constexpr (kSp == 0)
-                return e0 - gam * (hi[k] * Sr[k]);
-            else
-                return e0 + gam * (Sr[k] * Sr[k]);
-        };
         // the stash's last reads (own cells) are complete before lo lands there
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
         copy_to_lds<N, R, U, kLds>(lo + g.off(), stash, g);
@@ -261,14 +326,27 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             P[g.idx(k)] = hi[k];
             RD_GROUP_FENCE(k)
         }
+        // the other field's low part (level n, in the slot) joins its high
+        // part in the reaction coefficient; q is free until the predictor
+        const int o = g.off();
+#pragma unroll U
+        for (int k = 0; k < R; ++k)
+            q[k] = Slo[o + k * N];
         __syncthreads();
-        // r0 = src - e x - c t(x) for x = hi + lo, the same arithmetic as the
-        // two passes below
-        sweep_pair<N, R, U>(P, stash, g, [&](int k, Real own, Real t, Real lown, Real lt) {
-            const Real e = e_reg(k);
+        // r0 = src - e x - c t(x) for x = hi + lo and e from the other field
+        // hi + lo, in FP64: evaluated in FP32 its rounding (about 2^-24 of the
+        // reaction and diffusion terms) lies above rtol |b| at rtol 1e-9, and
+        // CG would spend iterations on that noise every step.  The operator
+        // of the CG itself stays FP32: its rounding enters only through the
+        // increment, far below the tolerance.
+        const double e0d = e0, gamd = gam, srcd = src, cd = c;
+        sweep_pair64<N, R, U>(P, stash, g, [&](int k, Real own, double t64, Real lown, Real lt) {
+            const double x64 = (double)own + (double)lown;
+            const double s64 = (double)Sr[k] + (double)q[k];
+            const double e = kSp == 0 ? e0d - gamd * (x64 * s64) : e0d + gamd * (s64 * s64);
             const Real b = own * inv_dt + src;
-            Real res = src - e * own - c * t;
-            res = res - (e * lown + c * lt);
+            const double res64 = (srcd - e * x64) - cd * (t64 + (double)lt);
+            Real res = (Real)res64;
             RD_PIN(res);
             r[k] = res;
             bb += (double)b * (double)b;
@@ -351,7 +429,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             RD_PIN(b2);
         });
         double v7[7] = {bb, rr, g11, g12, g22, b1, b2};
-        block_sum_n<NW>(v7, red + Slots<NW>::setup);
+        block_sum_n<NW>(v7, red + Slots<NW>::setup, g.wid);
         bb = v7[0];
         rr = v7[1];
         g11 = v7[2];
@@ -409,7 +487,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             RD_PIN(ww);
         });
         double v4[4] = {bb, rr, rw, ww};
-        block_sum_n<NW>(v4, red + Slots<NW>::setup);
+        block_sum_n<NW>(v4, red + Slots<NW>::setup, g.wid);
         bb = v4[0];
         rr = v4[1];
         rw = v4[2];
@@ -455,8 +533,8 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         // dependent accumulation chains.  With rr_pending, p = r here and
         // the same sweep sums r.r.
         double pq0 = 0.0, pq1 = 0.0, rp = 0.0;
-        sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
-            Real qq = c * t + sigma_at(k) * own;
+        sweep_nsum<N, R, U>(P, g, [&](int k, Real own, Real sn) {
+            Real qq = sigma4_at(k) * own - c * sn;
             RD_PIN(qq);
             q[k] = qq;
             if (k & 1) {
@@ -474,7 +552,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         double pq;
         if (rr_pending) {
             double v2[2] = {pq0 + pq1, rp};
-            block_sum_n<NW>(v2, red + Slots<NW>::setup);
+            block_sum_n<NW>(v2, red + Slots<NW>::setup, g.wid);
             pq = v2[0];
             rr = v2[1];
             rr_pending = false;
@@ -485,7 +563,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             if (!(rr > tol2))
                 break;  // the predictor alone met the tolerance
         } else {
-            pq = block_sum<NW>(pq0 + pq1, red + Slots<NW>::pq);
+            pq = block_sum<NW>(pq0 + pq1, red + Slots<NW>::pq, g.wid);
         }
         if (!finite(pq)) {
             st = kStNonfinite;
@@ -507,7 +585,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
                 rn0 += (double)v * (double)v;
             RD_GROUP_FENCE(k)
         }
-        const double rn = block_sum<NW>(rn0 + rn1, red + Slots<NW>::rr);
+        const double rn = block_sum<NW>(rn0 + rn1, red + Slots<NW>::rr, g.wid);
         ++it;
         if (!finite(rn)) {
             st = kStNonfinite;
@@ -691,7 +769,8 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
             LdsArr<Real, N> sv{stash + g.idx(0)};
             st = cg_solve<N, R, U, NW, kLds, 0, true, kPred2>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam,
                                                       rtol2, maxit, P, lo_u, hu_last, hu_new,
-                                                      npred_u, red, g, itu, quiet_u, &xv, stash);
+                                                      npred_u, red, g, itu, quiet_u, &xv, stash,
+                                                      lo_v);
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 xv[k] = sv[k];
@@ -700,7 +779,8 @@ __device__ int integrate(Arr &xu, Arr &xv, Arr &r, Arr &q, Arr &d, const double 
             store_increment<N, R, U>(d, hu_new, g);
             st = cg_solve<N, R, U, NW, kLds, 1, true, kPred2>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam,
                                                       rtol2, maxit, P, lo_v, hv_last, hv_new,
-                                                      npred_v, red, g, itv, quiet_v, &xu, stash);
+                                                      npred_v, red, g, itv, quiet_v, &xu, stash,
+                                                      lo_u);
 #pragma unroll U
             for (int k = 0; k < R; ++k)
                 xu[k] = sv[k];
@@ -1367,6 +1447,27 @@ __device__ __forceinline__ void sweep_coop(const float *P, const CoopGeo &g, F &
     }
 }
 
+// sweep_coop() with the plain neighbour sum (see sweep_nsum), for the CG
+// iteration on the increment.
+template <class F>
+__device__ __forceinline__ void sweep_coop_nsum(const float *P, const CoopGeo &g, F &&f)
+{
+    constexpr int N = kCoopN, R = kCoopR;
+    float cur = P[g.idx(0)];
+    float south = P[g.idx(0) - N];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const float north = P[g.idx(k) + N];
+        const float west = P[g.idx(k) - g.i + g.iw];
+        const float east = P[g.idx(k) - g.i + g.ie];
+        const float sn = (west + east) + (south + north);
+        f(k, cur, sn);
+        south = cur;
+        cur = north;
+        RD_GROUP_FENCE(k)
+    }
+}
+
 // Publish this member's edge rows of `field` (values v(k) of own cells).
 template <class V>
 __device__ __forceinline__ void coop_publish(const CoopCtx &x, int field, const CoopGeo &g, V &&v)
@@ -1419,6 +1520,13 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
         else
             return s0 + gam * (S[k] * S[k]);
     };
+    const float s04 = uniform(s0 + 4.0f * c);  // sigma + 4c: the neighbour-sum form
+    auto sigma4_at = [&](int k) -> float {
+        if constexpr (kSp == 0)
+            return s04 - gam * (hi[k] * S[k]);
+        else
+            return s04 + gam * (S[k] * S[k]);
+    };
     const float *lp = lo + g.off();
     const float *hp = H + g.off();
     // every field of the set-up travels before one barrier
@@ -1434,6 +1542,10 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
     coop_sync(x);
     coop_fetch_halo(x, kFieldHi, P);
     __syncthreads();
+    // r0 in FP32 (hi pass, then lo pass).  The resident tiles evaluate it in
+    // FP64, which saves CG iterations at rtol 1e-9; here the extra registers
+    // of that evaluation made the compiler spill inside the CG loop, which
+    // cost more than the iterations saved.
     double bb = 0.0, rr = 0.0;
     sweep_coop(P, g, [&](int k, float own, float t) {
         const float b = own * inv_dt + src;
@@ -1524,8 +1636,8 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
         }
         __syncthreads();  // p (own rows and halo) visible
         double pq = 0.0, rp = 0.0;
-        sweep_coop(P, g, [&](int k, float own, float t) {
-            float qq = c * t + sigma_at(k) * own;
+        sweep_coop_nsum(P, g, [&](int k, float own, float sn) {
+            float qq = sigma4_at(k) * own - c * sn;
             RD_PIN(qq);
             q[k] = qq;
             pq += (double)own * (double)qq;
