@@ -296,14 +296,16 @@ def agreement(tr_a, tr_b, names):
 
 
 def stationary_leg(args, u0, v0, y, sigma, gold, log):
-    """Plain vs delayed acceptance near stationarity at a CG tolerance that
-    resolves the posterior: proposal (Laplace covariance x 2.38^2/4) and
-    warm start from the Laplace approximation at the data-generating
-    parameters (the oracle's Hessian when stored, else the GPU's own),
-    surrogate trained on draws around it, the same wall-clock budget for
-    each sampler."""
+    """Plain random walk, one-proposal delayed acceptance and surrogate-chain
+    delayed acceptance near the posterior, run side by side: each sampler
+    has its own problem (workspace), stream and chains, the three step in
+    lockstep for the same wall-clock budget, so each gets the same number of
+    steps and a third of the GPU.  Random walk with the Laplace covariance x
+    2.38^2/4, warm start from the Laplace approximation at the
+    data-generating parameters (the oracle's Hessian when stored, else the
+    GPU's own), surrogate trained on draws around it."""
     import torch
-    from paper_1605_04718_amd import inputs, surrogate, stats
+    from paper_1605_04718_amd import inputs, surrogate
     from paper_1605_04718_amd.api import DA, PLAIN, ChainState, Grid, Problem
     n_steps = int(round(T_FINAL / TAU))
     C, S, rtol, budget = args.st_chains, args.st_steps, args.st_rtol, args.st_budget
@@ -323,110 +325,109 @@ def stationary_leg(args, u0, v0, y, sigma, gold, log):
     rng = np.random.default_rng(7)
     phi0 = c + rng.standard_normal((C, 4)) @ Lc.T
     log(f"stationary: Laplace ({src}) marginal s.d. {msd}")
-    p = Problem([Grid(n=N_CELLS, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, n_steps, rtol,
-                cg_maxit=2000, lo=LO, hi=HI, max_batch=max(C, 4096), prop_chol=Lp)
-    p.autotune()
+    use_chain = args.st_da_substeps > 1
+    names = ["plain", "da"] + (["chain"] if use_chain else [])
+    ps = {}
+    for nm in names:
+        ps[nm] = Problem([Grid(n=N_CELLS, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, n_steps, rtol,
+                         cg_maxit=2000, lo=LO, hi=HI,
+                         max_batch=max(C, 4096) if nm == "da" else C, prop_chol=Lp)
+        ps[nm].autotune()
     phi0_t = torch.tensor(phi0, dtype=torch.float64, device="cuda")
-    ll0, st0, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"))
+    ll0, _, _ = ps["plain"].log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"))
     torch.cuda.synchronize()
-    stream = torch.cuda.Stream()
-    ch = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER + 10,
-                           trace_steps=S)
-    plain = run_leg(p, ch, PLAIN, 0, S, stream, "stationary plain", budget_s=budget)
-    tr_p = ch.trace.cpu().numpy()[:plain["steps"]]
     # local surrogate: inputs mapped over +-8 posterior s.d., trained on draws
-    # spread three times wider than the Laplace approximation
-    p.surrogate_create(512, 4, 32, seed=inputs.SEED_SURROGATE_INIT)
-    p.surrogate_set_input_box(c - 8 * msd, c + 8 * msd)
+    # spread three times wider than the Laplace approximation; the chain
+    # sampler's problem gets a copy of the same network and scaling
+    box = (c - 8 * msd, c + 8 * msd)
+    ps["da"].surrogate_create(512, 4, 32, seed=inputs.SEED_SURROGATE_INIT)
+    ps["da"].surrogate_set_input_box(*box)
     draws = c + 3.0 * np.random.default_rng(8).standard_normal((args.st_sur_solves, 4)) @ Lc.T
-    draws = np.clip(draws, c - 8 * msd, c + 8 * msd)
+    draws = np.clip(draws, *box)
     t0 = time.time()
-    rep = surrogate.fit(p, sigma, LO, HI, len(draws), args.st_sur_epochs, log=log, phi=draws)
+    rep = surrogate.fit(ps["da"], sigma, LO, HI, len(draws), args.st_sur_epochs, log=log,
+                        phi=draws)
     fit_s = time.time() - t0
-    lls0 = p.surrogate_loglik(phi0_t)
+    if use_chain:
+        pc = ps["chain"]
+        pc.surrogate_create(512, 4, 32, seed=inputs.SEED_SURROGATE_INIT)
+        pc.surrogate_set_input_box(*box)
+        pc.surrogate_params(1, ps["da"].surrogate_params(0))
+        pc.surrogate_set_scaling(rep["scaling_mean"], rep["scaling_sd"], rep["sigma1"])
+        pc.set_da_substeps(args.st_da_substeps)
+    lls0 = ps["da"].surrogate_loglik(phi0_t)
     torch.cuda.synchronize()
-    chd = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER + 10,
-                            trace_steps=S, da=True)
-    chd.loglik_sur = lls0.clone()
-    da = run_leg(p, chd, DA, 0, S, stream, "stationary da", budget_s=budget)
-    tr_d = chd.trace.cpu().numpy()[:da["steps"]]
-    dac, tr_c = None, None
-    if args.st_da_substeps > 1:
-        # the first stage as a chain of Metropolis steps on the surrogate
-        # posterior: its end point goes to the full solve
-        p.set_da_substeps(args.st_da_substeps)
-        chc = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER + 10,
-                                trace_steps=S, da=True)
-        chc.loglik_sur = lls0.clone()
-        dac = run_leg(p, chc, DA, 0, S, stream, "stationary da chain", budget_s=budget)
-        tr_c = chc.trace.cpu().numpy()[:dac["steps"]]
-        p.set_da_substeps(1)
-    p.close()
-    names = ["a", "b", "ln_gamma", "ln_d"]
-    bp, bd = plain["steps"] // 2, da["steps"] // 2
-    ep = ess_block(tr_p[bp:], plain["wall"], max_rhat_ok=args.st_rhat_ok)
-    ed = ess_block(tr_d[bd:], da["wall"], max_rhat_ok=args.st_rhat_ok)
-    agree, worst = agreement(tr_p[bp:], tr_d[bd:], names)
-
-    def rate(e):
-        return e["ess_per_sec"] if e["ess_per_sec"] is not None else None
-
-    chain_block = None
-    if dac is not None:
-        bc = dac["steps"] // 2
-        ec = ess_block(tr_c[bc:], dac["wall"], max_rhat_ok=args.st_rhat_ok)
-        agree_c, worst_c = agreement(tr_p[bp:], tr_c[bc:], names)
-        chain_block = {
-            "substeps": args.st_da_substeps, "wall_s": dac["wall"], "steps": dac["steps"],
-            "accept_rate": dac["accepted"] / (C * dac["steps"]),
-            "reached_second_stage": dac["accepted1"] / (C * dac["steps"]),
-            "solves": dac["solves"], "failed_solves": fail_dict(dac["fail_bits"]), **ec,
-            "ess_per_sec_incl_surrogate_fit": (ec["min_bulk_ess"] / (dac["wall"] + fit_s)
-                                               if ec["min_bulk_ess"] and ec["ess_per_sec"]
-                                               else None),
-            "ess_per_solve": (ec["min_bulk_ess"] / dac["solves"] if ec["min_bulk_ess"] else None),
-            "ess_per_sec_speedup_vs_plain": (rate(ec) / rate(ep) if rate(ec) and rate(ep)
-                                             else None),
-            "ess_per_sec_speedup_vs_plain_raw": (ec["min_bulk_ess"] / dac["wall"] /
-                                                 (ep["min_bulk_ess"] / plain["wall"])
-                                                 if ec["min_bulk_ess"] and ep["min_bulk_ess"]
-                                                 else None),
-            "posterior_agreement_with_plain": {"max_diff_in_mcse": worst_c,
-                                               "matched_within_2_mcse": worst_c <= 2.0,
-                                               "per_parameter": agree_c},
-        }
-
+    chs, modes, streams = {}, {}, {}
+    for nm in names:
+        da = nm != "plain"
+        chs[nm] = ChainState.create(phi0_t.clone(), ll0.clone(), seed=inputs.SEED_SAMPLER + 10,
+                                    trace_steps=S, da=da)
+        if da:
+            chs[nm].loglik_sur = lls0.clone()
+        modes[nm] = DA if da else PLAIN
+        streams[nm] = torch.cuda.Stream()
+    c0 = {nm: chain_counts(chs[nm]) for nm in names}
+    torch.cuda.synchronize()
+    t0 = time.time()
+    steps = 0
+    while steps < S:
+        for nm in names:
+            with torch.cuda.stream(streams[nm]):
+                ps[nm].mcmc_step(chs[nm], 1, mode=modes[nm])
+        for nm in names:
+            streams[nm].synchronize()
+        steps += 1
+        el = time.time() - t0
+        log(f"stationary step {steps}: {el:.2f} s elapsed")
+        if el * (steps + 1) / steps > budget:
+            break
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    res = {}
+    for nm in names:
+        ps[nm].check_solves()
+        res[nm] = diff_counts(c0[nm], chain_counts(chs[nm]))
+        res[nm]["trace"] = chs[nm].trace.cpu().numpy()[:steps]
+        ps[nm].close()
+    pnames = ["a", "b", "ln_gamma", "ln_d"]
+    burn = steps // 2
+    blocks = {}
+    for nm in names:
+        r = res[nm]
+        e = ess_block(r["trace"][burn:], wall, max_rhat_ok=args.st_rhat_ok)
+        blk = {"steps": steps, "accept_rate": r["accepted"] / (C * steps), "solves": r["solves"],
+               "failed_solves": fail_dict(r["fail_bits"]), **e,
+               "ess_per_solve": (e["min_bulk_ess"] / r["solves"]
+                                 if e["min_bulk_ess"] and r["solves"] else None)}
+        if nm != "plain":
+            blk["reached_second_stage"] = r["accepted1"] / (C * steps)
+            blk["ess_per_sec_incl_surrogate_fit"] = (e["min_bulk_ess"] / (wall + fit_s)
+                                                     if e["min_bulk_ess"] else None)
+        if nm == "chain":
+            blk["substeps"] = args.st_da_substeps
+        blocks[nm] = blk
+    ep = blocks["plain"]
+    for nm in names[1:]:
+        b = blocks[nm]
+        b["ess_ratio_vs_plain"] = (b["min_bulk_ess"] / ep["min_bulk_ess"]
+                                   if b["min_bulk_ess"] and ep["min_bulk_ess"] else None)
+        agree, worst = agreement(res["plain"]["trace"][burn:], res[nm]["trace"][burn:], pnames)
+        b["posterior_agreement_with_plain"] = {"max_diff_in_mcse": worst,
+                                               "matched_within_2_mcse": worst <= 2.0,
+                                               "per_parameter": agree}
+    blocks["da"]["surrogate_held_out"] = rep["held_out"]
+    blocks["da"]["surrogate_fit_s"] = fit_s
     return {
-        "workload": f"{C} chains, 128x128, T=2, CG rtol {rtol}, correlated random walk with "
-                    "the Laplace covariance x 2.38^2/4, warm start from the Laplace "
-                    f"approximation at the data-generating parameters ({src}); each sampler "
-                    f"runs for {budget:g} s of wall time (at most {S} steps), the first half "
-                    "of each chain is discarded",
+        "workload": f"{C} chains per sampler, the samplers side by side ({len(names)} problems, "
+                    "streams and chain sets stepping in lockstep), 128x128, T=2, CG rtol "
+                    f"{rtol}, correlated random walk with the Laplace covariance x 2.38^2/4, "
+                    "warm start from the Laplace approximation at the data-generating "
+                    f"parameters ({src}); {steps} steps in {wall:.1f} s of shared wall time, the "
+                    "first half of each chain discarded; ESS/s = min bulk-ESS / shared wall time",
         "laplace_marginal_sd": msd.tolist(),
-        "plain": {"wall_s": plain["wall"], "steps": plain["steps"],
-                  "accept_rate": plain["accepted"] / (C * plain["steps"]),
-                  "solves": plain["solves"], "failed_solves": fail_dict(plain["fail_bits"]),
-                  **ep,
-                  "ess_per_solve": (ep["min_bulk_ess"] / plain["solves"]
-                                    if ep["min_bulk_ess"] else None)},
-        "da": {"wall_s": da["wall"], "steps": da["steps"],
-               "accept_rate": da["accepted"] / (C * da["steps"]),
-               "stage1_accept_rate": da["accepted1"] / (C * da["steps"]), "solves": da["solves"],
-               "failed_solves": fail_dict(da["fail_bits"]),
-               "surrogate_held_out": rep["held_out"], "surrogate_fit_s": fit_s, **ed,
-               "ess_per_sec_incl_surrogate_fit": (ed["min_bulk_ess"] / (da["wall"] + fit_s)
-                                                  if ed["min_bulk_ess"] and ed["ess_per_sec"]
-                                                  else None),
-               "ess_per_solve": (ed["min_bulk_ess"] / da["solves"]
-                                 if ed["min_bulk_ess"] else None)},
-        "ess_per_sec_speedup": (rate(ed) / rate(ep) if rate(ed) and rate(ep) else None),
-        "ess_per_sec_speedup_raw": (ed["min_bulk_ess"] / da["wall"] /
-                                    (ep["min_bulk_ess"] / plain["wall"])
-                                    if ed["min_bulk_ess"] and ep["min_bulk_ess"] else None),
-        "posterior_agreement": {"a": "plain", "b": "delayed acceptance",
-                                "max_diff_in_mcse": worst, "matched_within_2_mcse": worst <= 2.0,
-                                "per_parameter": agree},
-        "da_surrogate_chain": chain_block,
+        "wall_s": wall, "steps": steps,
+        "plain": blocks["plain"], "da": blocks["da"],
+        "da_surrogate_chain": blocks.get("chain"),
     }
 
 
@@ -831,12 +832,13 @@ def main():
                          "(16 prior draws, T = 2)")
     ap.add_argument("--no-stationary", action="store_true",
                     help="skip plain vs delayed acceptance near stationarity (ESS/s)")
-    ap.add_argument("--st-chains", type=int, default=256,
-                    help="chains of the stationary leg (one per CU: each step costs about one "
-                         "solve, so the budget buys the most steps per chain)")
+    ap.add_argument("--st-chains", type=int, default=84,
+                    help="chains per sampler in the stationary leg (the three samplers run side "
+                         "by side, one chain per CU: each step costs about one solve, so the "
+                         "budget buys the most steps per chain)")
     ap.add_argument("--st-steps", type=int, default=400, help="step cap of each stationary run")
-    ap.add_argument("--st-budget", type=float, default=30.0,
-                    help="wall-clock seconds of each stationary sampler run")
+    ap.add_argument("--st-budget", type=float, default=110.0,
+                    help="wall-clock seconds of the stationary leg's side-by-side run")
     ap.add_argument("--st-rtol", type=float, default=1e-9)
     ap.add_argument("--st-rhat-ok", type=float, default=1.05,
                     help="ESS/s is reported as a rate only below this split-R-hat")

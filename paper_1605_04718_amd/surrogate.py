@@ -196,6 +196,7 @@ def fit(p, sigma, lo, hi, solves, epochs, batch=1024, lr=1e-3, held_out=0.05, lo
         "train_seconds": train_s, "train_tflops": train_flops / train_s / 1e12 if train_s else None,
         "final_train_mse": history[-1] if history else None, "loss_history": history,
         "held_out": err, "sigma1": sig1,
+        "scaling_mean": mean, "scaling_sd": sd,   # device tensors (not for JSON)
     }
 
 
@@ -229,6 +230,8 @@ def _main(argv=None):
     p.autotune()
     p.surrogate_create(512, 4, 32, seed=inputs.SEED_SURROGATE_INIT)
     rep = fit(p, sigma, lo, hi, args.solves, args.epochs, batch=args.batch, lr=args.lr, log=log)
+    rep.pop("scaling_mean")
+    rep.pop("scaling_sd")
     rep["grid"] = args.n
     rep["workload"] = (f"{args.solves} prior draws solved at {args.n}x{args.n} to T = 2 "
                        f"(dt 2.5e-4) -> 32x32 block means; MLP 4-512x4-1024 GELU, BF16 MFMA")
