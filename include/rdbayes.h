@@ -253,7 +253,10 @@ typedef struct {
  * purpose 2; only first-stage accepts are solved; the second stage accepts
  * iff log U < [Phi(phi) - Phi(phi')] - [Phi~(phi) - Phi~(phi')].
  * On a created stream the steps are replayed from one captured HIP graph per
- * chains layout; on the null stream they are launched directly.
+ * chains layout, mode and stream: the layout's first step runs as direct
+ * launches, the next one (in the same call or a later one) is captured and
+ * every later step replays it; on the null stream, and while
+ * rd_solver_timing is on, steps are launched directly.
  * chains->step is advanced by n_steps on return (host field).  The trace
  * keeps one row per step across calls (row = step - trace_step0).
  * Errors: RD_EINVAL (shapes, NULL required arrays), RD_EUNSUPPORTED (DA

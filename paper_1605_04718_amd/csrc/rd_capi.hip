@@ -168,6 +168,9 @@ struct rd_problem {
     int64_t launches = 0;
     // captured MCMC steps
     std::vector<GraphEntry> graphs;
+    // layouts (chains, mode, stream) whose step has run once directly since
+    // the graphs were last dropped: the next step of such a layout is captured
+    std::vector<GraphEntry> warm;
     bool use_graphs = true;
     // surrogate
     Surrogate *sur = nullptr;
@@ -496,6 +499,7 @@ void drop_graphs(rd_problem *p)
             hipGraphDestroy(g.graph);
     }
     p->graphs.clear();
+    p->warm.clear();
 }
 
 }  // namespace
@@ -872,13 +876,26 @@ extern "C" int32_t mcmc_step_batch(rd_problem *p, rd_chains *chains, int32_t n_s
     if (!ge) {
         // The first step of a new layout runs as direct launches, so every
         // kernel of the sequence has been loaded and launched once before
-        // capture begins; capture then records launches only.
-        if ((r = enqueue_mcmc_step(p, chains, mode, s)) != RD_OK)
-            return r;
-        done = 1;
-        if (done == n_steps) {
-            chains->step += (uint64_t)n_steps;
-            return RD_OK;
+        // capture begins; capture then records launches only.  The layout
+        // is remembered, so that with one step per call the second call
+        // captures.
+        bool warm = false;
+        for (auto &w : p->warm)
+            if (same_chains(w.key, *chains) && w.mode == mode && w.stream == s)
+                warm = true;
+        if (!warm) {
+            if ((r = enqueue_mcmc_step(p, chains, mode, s)) != RD_OK)
+                return r;
+            GraphEntry w;
+            w.key = *chains;
+            w.mode = mode;
+            w.stream = s;
+            p->warm.push_back(w);
+            done = 1;
+            if (done == n_steps) {
+                chains->step += (uint64_t)n_steps;
+                return RD_OK;
+            }
         }
         GraphEntry g;
         g.key = *chains;

@@ -389,3 +389,50 @@ def test_surrogate_chain_decisions_match_the_oracle():
         compared += 1
     assert compared > C // 3
     p.close()
+
+
+def test_one_step_calls_replay_graphs_and_match_direct_launches():
+    """With one Metropolis step per call on a created stream, the first call
+    of a layout runs directly, the second captures, the rest replay; plain
+    steps, one-proposal delayed acceptance and a three-substep surrogate
+    chain must give the chains of direct launches on the null stream bit
+    for bit."""
+    import torch
+    from paper_1605_04718_amd.api import DA, PLAIN, ChainState
+    need_gpu()
+    step = np.array([0.01, 0.01, 0.02, 0.02])
+    p, u0, v0, y, sigma = small_problem(step=step, precision=1, steps=6)
+    p.surrogate_set_scaling(torch.ones(64, device="cuda"), torch.full((64,), 0.05, device="cuda"),
+                            0.2)
+    C, S = 48, 5
+    phi0 = np.tile(inputs.to_sampling(THETA_TRUE)[0], (C, 1))
+    phi0[:, 0] += np.linspace(-0.02, 0.02, C)
+    ll0, _, _ = p.log_likelihood(torch.tensor(inputs.to_natural(phi0), device="cuda"))
+    lls0 = p.surrogate_loglik(torch.tensor(phi0, device="cuda"))
+    torch.cuda.synchronize()
+
+    def chains(da):
+        ch = ChainState.create(torch.tensor(phi0, device="cuda"), ll0.clone(), seed=41,
+                               trace_steps=S, da=da)
+        if da:
+            ch.loglik_sur = lls0.clone()
+        return ch
+
+    side = torch.cuda.Stream()
+    for m, mode in ((1, PLAIN), (1, DA), (3, DA)):
+        p.set_da_substeps(m)
+        ref = chains(mode == DA)
+        p.mcmc_step(ref, S, mode=mode)   # null stream: direct launches
+        torch.cuda.synchronize()
+        ch = chains(mode == DA)
+        assert p.captured_graphs() == 0
+        with torch.cuda.stream(side):
+            for k in range(S):
+                p.mcmc_step(ch, 1, mode=mode)
+                side.synchronize()
+                assert p.captured_graphs() == (0 if k == 0 else 1), (m, mode, k)
+        assert torch.equal(ch.phi, ref.phi) and torch.equal(ch.loglik, ref.loglik), (m, mode)
+        assert torch.equal(ch.trace, ref.trace) and torch.equal(ch.n_solves, ref.n_solves)
+        if mode == DA:
+            assert torch.equal(ch.loglik_sur, ref.loglik_sur)
+    p.close()
