@@ -1503,7 +1503,7 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
                        RegArr<float, kCoopR> &d, float inv_dt, float c, float src, float dl,
                        float gam, double rtol2, int maxit, float *P, const float *lo,
                        const float *H, bool pred, double *red, const CoopGeo &g, CoopCtx &x,
-                       int &it_acc)
+                       int &it_acc, const float *Slo)
 {
     constexpr int R = kCoopR, NW = kCoopThreads / kWave;
     const float e0 = uniform(kSp == 0 ? dl + gam : dl);
@@ -1547,9 +1547,17 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
     // of that evaluation made the compiler spill inside the CG loop, which
     // cost more than the iterations saved.
     double bb = 0.0, rr = 0.0;
+    const float *slp = Slo + g.off();
+    const double e0d = e0, gamd = gam;
     sweep_coop(P, g, [&](int k, float own, float t) {
         const float b = own * inv_dt + src;
-        float res = src - e_at(k) * own - c * t;
+        // the reaction coefficient from both fields' hi + lo in FP64,
+        // rounded once: 1 - u v cancels, and in FP32 its rounding noise lay
+        // above rtol |b|
+        const double x64 = (double)own + (double)lp[k * kCoopN];
+        const double s64 = (double)S[k] + (double)slp[k * kCoopN];
+        const float e = (float)(kSp == 0 ? e0d - gamd * (x64 * s64) : e0d + gamd * (s64 * s64));
+        float res = src - e * own - c * t;
         RD_PIN(res);
         r[k] = res;
         bb += (double)b * (double)b;
@@ -1803,7 +1811,7 @@ __device__ void solve_item_coop(const SolveArgs &a, int c, const GridDev &gd, fl
         for (int k = 0; k < R; ++k)
             sv[k] = xv[k];
         st = cg_coop<0>(xu, sv, r, q, d, inv_dt, cu, src_u, dl, gam, a.rtol2, a.maxit, P, lo_u,
-                        h_u, pred_u, red, g, x, itu);
+                        h_u, pred_u, red, g, x, itu, lo_v);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             xv[k] = sv[k];
@@ -1819,7 +1827,7 @@ __device__ void solve_item_coop(const SolveArgs &a, int c, const GridDev &gd, fl
                 h_u[o + k * N] = d[k];
         }
         st = cg_coop<1>(xv, sv, r, q, d, inv_dt, cv, src_v, dl, gam, a.rtol2, a.maxit, P, lo_v,
-                        h_v, pred_v, red, g, x, itv);
+                        h_v, pred_v, red, g, x, itv, lo_u);
 #pragma unroll
         for (int k = 0; k < R; ++k)
             xu[k] = sv[k];
@@ -1920,7 +1928,7 @@ __device__ void coop_drain(const SolveArgs &a, bool prefix_only, unsigned *queue
 // the 256^2 items form its prefix: a group stops at the first item of
 // another class (or with an invalid class, which sorts last); a following
 // launch serves the rest.
-__device__ void coop_run(const SolveArgs &a, bool prefix_only, float *P, float *stash,
+__device__ __forceinline__ void coop_run(const SolveArgs &a, bool prefix_only, float *P, float *stash,
                          double *red, double *gather, int *fail, int *s_item)
 {
     // group of this workgroup: ids congruent modulo 8 share an XCD
