@@ -843,6 +843,8 @@ def main():
     ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--da-warmup", type=int, default=2,
                     help="warm-up steps of the delayed-acceptance leg (at most --warmup)")
+    ap.add_argument("--legacy-steps", type=int, default=5,
+                    help="timed steps of the plain leg at the earlier CG rtol 1e-7 (0: skip)")
     ap.add_argument("--da-steps", type=int, default=10,
                     help="timed steps of the delayed-acceptance leg (at most --steps)")
     ap.add_argument("--no-mixed", action="store_true",
@@ -1062,6 +1064,26 @@ def main():
     def mark(name):
         legs[name] = time.time() - t_start - sum(legs.values())
         log(f"{name}: {legs[name]:.1f} s ({time.time() - t_start:.1f} s since start)")
+
+    if args.legacy_steps > 0:
+        # the previous headline setting (CG rtol 1e-7, cap 400), for
+        # comparison with earlier measurements of the same kernel family
+        pl = Problem([Grid(n=N_CELLS, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, n_steps, 1e-7,
+                     cg_maxit=400, lo=LO, hi=HI, step=step, max_batch=C)
+        pl.autotune()
+        l0, _, _ = pl.log_likelihood(th0)
+        chl = ChainState.create(phi0_t.clone(), l0.clone(), seed=inputs.SEED_SAMPLER)
+        leg = run_leg(pl, chl, PLAIN, 2, args.legacy_steps, stream, "plain rtol 1e-7")
+        pl.close()
+        line["plain_rtol_1e-7"] = {
+            "warmup": 2, "steps": leg["steps"], "ms_per_step": 1e3 * leg["wall"] / leg["steps"],
+            "cell_steps_per_s": cells * leg["imex_steps"] / leg["wall"],
+            "cg_iters_per_step": {"u": leg["iters"][0] / max(leg["imex_steps"], 1),
+                                  "v": leg["iters"][1] / max(leg["imex_steps"], 1)},
+            "failed_solves": fail_dict(leg["fail_bits"]),
+            "note": "the same chains from prior draws at the earlier headline setting (CG rtol "
+                    "1e-7, cap 400), which does not resolve the posterior (loglik_error block)"}
+        mark("plain_rtol_1e-7")
 
     if gold is not None and not args.no_loglik_error:
         line["loglik_error"] = loglik_error_leg(gold, u0, v0,
