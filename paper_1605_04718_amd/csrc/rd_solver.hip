@@ -243,6 +243,11 @@ struct Slots {
 // FP32 rounding of its own terms, CG solves for the increment of the step
 // (a small quantity, well represented in FP32), and the increment is folded
 // back into hi + lo without loss.
+// Squared CG tolerance below which the resident FP32 solve evaluates its
+// step residual in FP64 (rtol < 3e-8: ten times the FP32 evaluation's
+// rounding floor relative to |b|).
+constexpr double kRes64Rtol2 = 9e-16;
+
 template <typename Real>
 struct Compensated {
     static constexpr bool on = sizeof(Real) == 4;
@@ -318,6 +323,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
     double bb = 0.0, rr = 0.0;
     if constexpr (kFuse) {
         const Arr &Sr = *Sreg;
+        const bool use64 = rtol2 < kRes64Rtol2;
         // the stash's last reads (own cells) are complete before lo lands there
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
         copy_to_lds<N, R, U, kLds>(lo + g.off(), stash, g);
@@ -326,34 +332,60 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             P[g.idx(k)] = hi[k];
             RD_GROUP_FENCE(k)
         }
-        // the other field's low part (level n, in the slot) joins its high
-        // part in the reaction coefficient; q is free until the predictor
-        const int o = g.off();
-#pragma unroll U
-        for (int k = 0; k < R; ++k)
-            q[k] = Slo[o + k * N];
-        __syncthreads();
-        // r0 = src - e x - c t(x) for x = hi + lo and e from the other field
-        // hi + lo, in FP64: evaluated in FP32 its rounding (about 2^-24 of the
-        // reaction and diffusion terms) lies above rtol |b| at rtol 1e-9, and
-        // CG would spend iterations on that noise every step.  The operator
-        // of the CG itself stays FP32: its rounding enters only through the
+        // r0 = src - e x - c t(x) for x = hi + lo.  Evaluated in FP32 its
+        // rounding (about 2^-24 of the reaction and diffusion terms, 2-3e-9
+        // of |b|) lies above rtol |b| once rtol drops below about 3e-8, and
+        // CG would spend iterations on that noise every step; there it is
+        // evaluated in FP64, with e from the other field's hi + lo too.
+        // At looser tolerances the FP32 form costs less.  The operator of the
+        // CG itself stays FP32: its rounding enters only through the
         // increment, far below the tolerance.
-        const double e0d = e0, gamd = gam, srcd = src, cd = c;
-        sweep_pair64<N, R, U>(P, stash, g, [&](int k, Real own, double t64, Real lown, Real lt) {
-            const double x64 = (double)own + (double)lown;
-            const double s64 = (double)Sr[k] + (double)q[k];
-            const double e = kSp == 0 ? e0d - gamd * (x64 * s64) : e0d + gamd * (s64 * s64);
-            const Real b = own * inv_dt + src;
-            const double res64 = (srcd - e * x64) - cd * (t64 + (double)lt);
-            Real res = (Real)res64;
-            RD_PIN(res);
-            r[k] = res;
-            bb += (double)b * (double)b;
-            rr += (double)res * (double)res;
-            RD_PIN(bb);
-            RD_PIN(rr);
-        });
+        if (use64) {
+            // the other field's low part (level n, in the slot; q is free
+            // until the predictor).  Loaded here, not ahead of the copy of
+            // lo: held across it, the 16 registers made the compiler spill
+            // inside the CG loop.
+            const int o = g.off();
+#pragma unroll U
+            for (int k = 0; k < R; ++k)
+                q[k] = Slo[o + k * N];
+            __syncthreads();
+            const double e0d = e0, gamd = gam, srcd = src, cd = c;
+            sweep_pair64<N, R, U>(P, stash, g, [&](int k, Real own, double t64, Real lown, Real lt) {
+                const double x64 = (double)own + (double)lown;
+                const double s64 = (double)Sr[k] + (double)q[k];
+                const double e = kSp == 0 ? e0d - gamd * (x64 * s64) : e0d + gamd * (s64 * s64);
+                const Real b = own * inv_dt + src;
+                const double res64 = (srcd - e * x64) - cd * (t64 + (double)lt);
+                Real res = (Real)res64;
+                RD_PIN(res);
+                r[k] = res;
+                bb += (double)b * (double)b;
+                rr += (double)res * (double)res;
+                RD_PIN(bb);
+                RD_PIN(rr);
+            });
+        } else {
+            __syncthreads();
+            auto e_reg = [&](int k) -> Real {
+                if constexpr (kSp == 0)
+                    return e0 - gam * (hi[k] * Sr[k]);
+                else
+                    return e0 + gam * (Sr[k] * Sr[k]);
+            };
+            sweep_pair<N, R, U>(P, stash, g, [&](int k, Real own, Real t, Real lown, Real lt) {
+                const Real e = e_reg(k);
+                const Real b = own * inv_dt + src;
+                Real res = src - e * own - c * t;
+                res = res - (e * lown + c * lt);
+                RD_PIN(res);
+                r[k] = res;
+                bb += (double)b * (double)b;
+                rr += (double)res * (double)res;
+                RD_PIN(bb);
+                RD_PIN(rr);
+            });
+        }
         __syncthreads();  // every stencil read of P and of the stash is done
 #pragma unroll U
         for (int k = 0; k < R; ++k)
