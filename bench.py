@@ -40,6 +40,8 @@ import os
 import sys
 import time
 
+T_PROCESS0 = time.time()   # the run's clock starts before torch is imported
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -843,6 +845,9 @@ def main():
     ap.add_argument("--sur-epochs", type=int, default=40)
     ap.add_argument("--da-warmup", type=int, default=2,
                     help="warm-up steps of the delayed-acceptance leg (at most --warmup)")
+    ap.add_argument("--time-limit", type=float, default=560.0,
+                    help="seconds from process start within which the run must end: the legs "
+                         "after the headline are shortened or dropped to fit")
     ap.add_argument("--legacy-steps", type=int, default=5,
                     help="timed steps of the plain leg at the earlier CG rtol 1e-7 (0: skip)")
     ap.add_argument("--da-steps", type=int, default=10,
@@ -1065,7 +1070,22 @@ def main():
         legs[name] = time.time() - t_start - sum(legs.values())
         log(f"{name}: {legs[name]:.1f} s ({time.time() - t_start:.1f} s since start)")
 
-    if args.legacy_steps > 0:
+    skipped = []
+
+    def remaining():
+        return args.time_limit - (time.time() - T_PROCESS0)
+
+    def room(name, need):
+        """Whether a leg that takes about `need` seconds fits the run's time
+        limit (the legs after the headline are dropped, last first, rather
+        than let the run overrun its envelope)."""
+        if remaining() >= need:
+            return True
+        skipped.append(name)
+        log(f"{name}: skipped, {remaining():.0f} s left of the {args.time_limit:.0f} s limit")
+        return False
+
+    if args.legacy_steps > 0 and room("plain_rtol_1e-7", 40 + 200):
         # the previous headline setting (CG rtol 1e-7, cap 400), for
         # comparison with earlier measurements of the same kernel family
         pl = Problem([Grid(n=N_CELLS, u0=u0, v0=v0, y=y, sigma=sigma)], TAU, n_steps, 1e-7,
@@ -1090,9 +1110,17 @@ def main():
                                                 sorted({1e-7, CG_RTOL, args.st_rtol}), log)
         mark("loglik_error")
     if not args.no_stationary:
-        line["stationary"] = stationary_leg(args, u0, v0, y, sigma, gold, log)
-        mark("stationary")
-    if not args.no_mixed:
+        # keep about 170 s for the uneven leg, config 1 and the CPU baseline
+        budget = min(args.st_budget, remaining() - 170.0 - 20.0)
+        if budget >= 30.0:
+            if budget < args.st_budget:
+                log(f"stationary: budget cut to {budget:.0f} s by the time limit")
+            args.st_budget = budget
+            line["stationary"] = stationary_leg(args, u0, v0, y, sigma, gold, log)
+            mark("stationary")
+        else:
+            room("stationary", float("inf"))
+    if not args.no_mixed and room("mixed", 150.0):
         line["mixed"] = mixed_leg(args, log)
         mark("mixed")
     if args.precision_256:
@@ -1100,11 +1128,11 @@ def main():
     if args.growth1d:
         line["growth1d"] = growth1d_leg(args, log)
     trace_gpu = None
-    if not args.no_config1:
+    if not args.no_config1 and room("config1", 25.0):
         line["config1"], trace_gpu = config1_gpu_leg(log)
         mark("config1")
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and room("cpu_baseline", 20.0):
         threads = cpu_threads()
         log(f"cpu baseline: oracle on {threads} threads")
         line["cpu_baseline"] = cpu_baseline(u0, v0, y, sigma, args.cpu_sample_steps, threads)
@@ -1137,6 +1165,8 @@ def main():
         "the stated steps; the CPU's full-solve rate and ESS/s are extrapolated or derived and "
         "labelled so")
     line["leg_seconds"] = legs
+    line["legs_skipped_for_time"] = skipped
+    line["process_seconds"] = time.time() - T_PROCESS0
     print(json.dumps(line), flush=True)
 
 
