@@ -119,6 +119,53 @@ __device__ __forceinline__ int wave_index()
     return uniform((int)(threadIdx.x / kWave));
 }
 
+__device__ __forceinline__ double readlane_f64(double x, int lane)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// This lane's index in its wave, computed where it is used: the large
+// solve kernels keep no VGPR for it across their loops (a loop-invariant
+// value derived from the thread index and held across the CG loop is what
+// their register allocator spills; a volatile asm is not hoisted).
+__device__ __forceinline__ int lane_here()
+{
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
+// The workgroup totals of M values from the per-wave totals in
+// slot[m kWaves + w]: row m of the wave (lanes 16m .. 16m + 15) reads value
+// m's kWaves totals in one LDS access and adds them with the four row_shr
+// steps of wave_sum_last_lane, so the sum costs one LDS round trip per four
+// values (a loop over the slots waits for each load in turn).  The order of
+// additions is fixed and the same in every wave; the results are
+// wave-uniform (scalar registers).
+template <int kWaves, int M>
+__device__ __forceinline__ void slots_sum(double (&v)[M], const double *slot)
+{
+    static_assert(kWaves <= 16, "one 16-lane row per value");
+    const int lane = lane_here();
+    const int row = lane >> 4, w = lane & 15;
+#pragma unroll
+    for (int m0 = 0; m0 < M; m0 += 4) {
+        double x = 0.0;
+        if (m0 + row < M && w < kWaves)
+            x = slot[(m0 + row) * kWaves + w];
+        x += dpp_f64<0x111, 0xF>(x);  // row_shr:1
+        x += dpp_f64<0x112, 0xF>(x);  // row_shr:2
+        x += dpp_f64<0x114, 0xF>(x);  // row_shr:4
+        x += dpp_f64<0x118, 0xF>(x);  // row_shr:8 -> lane 15 of the row: its sum
+#pragma unroll
+        for (int m = m0; m < M && m < m0 + 4; ++m)
+            v[m] = readlane_f64(x, 16 * (m - m0) + 15);
+    }
+}
+
 template <int kWaves>
 __device__ __forceinline__ double block_sum(double v, double *slot, int wid)
 {
@@ -127,11 +174,9 @@ __device__ __forceinline__ double block_sum(double v, double *slot, int wid)
     if (lane == kLastLane)
         slot[wid] = v;
     __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w)
-        s += slot[w];
-    return uniform(s);
+    double s[1];
+    slots_sum<kWaves>(s, slot);
+    return s[0];
 }
 
 template <int kWaves>
@@ -152,14 +197,10 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *slot)
         slot[kWaves + wid] = b;
     }
     __syncthreads();
-    double sa = 0.0, sb = 0.0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        sa += slot[w];
-        sb += slot[kWaves + w];
-    }
-    a = uniform(sa);
-    b = uniform(sb);
+    double s[2];
+    slots_sum<kWaves>(s, slot);
+    a = s[0];
+    b = s[1];
 }
 
 template <int kWaves, int M>
@@ -175,14 +216,7 @@ __device__ __forceinline__ void block_sum_n(double (&v)[M], double *slot, int wi
             slot[m * kWaves + wid] = v[m];
     }
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w)
-            s += slot[m * kWaves + w];
-        v[m] = uniform(s);
-    }
+    slots_sum<kWaves>(v, slot);
 }
 
 template <int kWaves, int M>

@@ -1389,16 +1389,17 @@ __device__ void coop_sum(double (&v)[M], double *red, CoopCtx &x)
             red[m * NW + t / kWave] = v[m];
     }
     __syncthreads();
+    double own[M];
+    slots_sum<NW>(own, red);  // this member's sums (wave-uniform)
     x.seq += 1;
     const unsigned tag = x.seq & 0xFFu;
     double *buf = x.partial(x.seq);
     if (t < 4) {  // lanes 0..3 publish this member's four slots (zero past M)
         double sum = 0.0;
-        if (t < M) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w)
-                sum += red[t * NW + w];
-        }
+        for (int q = 0; q < M; ++q)
+            if (t == q)
+                sum = own[q];
         const double pub = with_tag(sum, tag);
         coop_store(buf + lane_off(x.m * 4 + t), pub);
         if (t < M)
