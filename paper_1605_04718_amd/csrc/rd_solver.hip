@@ -246,6 +246,21 @@ struct Slots {
 // Squared CG tolerance below which the resident FP32 solve evaluates its
 // step residual in FP64 (rtol < 3e-8: ten times the FP32 evaluation's
 // rounding floor relative to |b|).
+// The CG step lengths alpha = rr / pq and beta = rn / rr (FP64 sums) in
+// the working precision.  FP32 tiles take them from the hardware reciprocal
+// (within 1 ulp) times the numerator, about 1.5 ulp in all: the iteration
+// updates r and d with the same value, so the recursion stays consistent,
+// and the FP64 division (a chain of about ten dependent operations) sat on
+// the path every wave of the workgroup waits on after each reduction.
+template <typename Real>
+__device__ __forceinline__ Real step_ratio(double num, double den)
+{
+    if constexpr (sizeof(Real) == 4)
+        return uniform((float)num * __builtin_amdgcn_rcpf((float)den));
+    else
+        return uniform(num / den);
+}
+
 constexpr double kRes64Rtol2 = 9e-16;
 
 template <typename Real>
@@ -605,7 +620,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             st = kStBreakdown;
             break;
         }
-        const Real a = uniform((Real)(rr / pq));
+        const Real a = step_ratio<Real>(rr, pq);
         double rn0 = 0.0, rn1 = 0.0;
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
@@ -623,7 +638,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
             st = kStNonfinite;
             break;
         }
-        const Real bt = uniform((Real)(rn / rr));
+        const Real bt = step_ratio<Real>(rn, rr);
         // d += alpha p_old and p = r + beta p_old (own cells only; the
         // stencil reads of p finished before the p.q barrier).
 #pragma unroll U
@@ -1709,7 +1724,7 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
             st = kStBreakdown;
             break;
         }
-        const float a = uniform((float)(rr / pq));
+        const float a = step_ratio<float>(rr, pq);
         double rn = 0.0;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -1727,7 +1742,7 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
             st = kStNonfinite;
             break;
         }
-        const float bt = uniform((float)(rn / rr));
+        const float bt = step_ratio<float>(rn, rr);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const float p = P[g.idx(k)];
