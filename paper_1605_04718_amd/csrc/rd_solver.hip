@@ -451,13 +451,23 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         copy_to_lds<N, R, U, kLds>(H1 + g.off(), P, g);
         __syncthreads();
         const Real *h2 = H2 + g.off();
+        // H2's own cells are loaded a group of cells at a time, at the
+        // group's first cell: loaded at each cell, between the pinned sums,
+        // every load was waited for before the next (one global round trip
+        // per cell); a window of more cells ahead made the compiler spill
         double g11 = 0.0, g12 = 0.0, b1 = 0.0;
+        Real h2g[kGroup];
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
+            if (k % kGroup == 0) {
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j)
+                    h2g[j] = k + j < R ? h2[(k + j) * N] : Real(0);
+            }
             Real w = c * t + sigma_at(k) * own;  // (A H1) at the cell
             RD_PIN(w);
             const double wd = (double)w;
             g11 += (double)own * wd;
-            g12 += (double)h2[k * N] * wd;        // (H2, A H1) = (H1, A H2)
+            g12 += (double)h2g[k % kGroup] * wd;  // (H2, A H1) = (H1, A H2)
             b1 += (double)own * (double)r[k];
             RD_PIN(g11);
             RD_PIN(g12);
@@ -498,9 +508,15 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         // d0 = w1 H1 + w2 H2 (own cells; the reduction barrier ended the
         // stencil reads of H2), then r0 - A d0 from its stencil
         const Real *h1 = H1 + g.off();
+        Real hg[kGroup];  // H1's own cells, a group at a time (as H2 above)
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
-            Real dk = W1 * h1[k * N];
+            if (k % kGroup == 0) {
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j)
+                    hg[j] = k + j < R ? h1[(k + j) * N] : Real(0);
+            }
+            Real dk = W1 * hg[k % kGroup];
             dk = dk + W2 * P[g.idx(k)];
             RD_PIN(dk);
             d[k] = dk;
