@@ -91,13 +91,14 @@ FLOP_OVERHEAD_STEP = 12.0 + 9.0 + 17.0
 FLOP_OVERHEAD_ITER = 3.0
 # HBM bytes of the fused solve kernel from two rocprofv3 PMC passes over the
 # timed step of `bench.py --steps 1 --warmup 0 --no-da --no-cpu-baseline
-# --no-mixed --no-stationary --no-config1 --no-loglik-error` at CG rtol 1e-9
-# (3831 solves, 29 438 831 completed solve-steps): FETCH_SIZE 5 351 000 000 KiB
-# x 2.00 + WRITE_SIZE 7 475 000 000 KiB x 1.00 (factors from a 256 MiB copy),
-# per completed solve-step.  Valid only for the kernel version and tile it was
-# measured on (step residual in FP64 below rtol 3e-8, two-increment CG start;
-# the queue order does not change what a solve reads or writes).
-MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 632268.6}
+# --no-mixed --no-stationary --no-config1 --no-loglik-error --legacy-steps 0`
+# at CG rtol 1e-9 (3831 solves, 29 438 831 completed solve-steps): FETCH_SIZE
+# 5 556 000 000 KiB x 2.00 + WRITE_SIZE 7 478 000 000 KiB x 1.00 (factors from a
+# 256 MiB copy), per completed solve-step.  Valid only for the kernel version
+# and tile it was measured on (step residual in FP64 below rtol 3e-8,
+# two-increment CG start with grouped history loads, row-summed workgroup
+# reductions; the queue order does not change what a solve reads or writes).
+MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 646634.4}
 STATUS_BITS = ["not_converged", "breakdown", "nonfinite", "out_of_prior", "bad_grid",
                "not_steady", "group_timeout", "bit7"]
 GOLDEN = os.path.join(ROOT, "tests", "golden", "loglik_64.npz")
