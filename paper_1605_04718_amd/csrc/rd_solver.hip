@@ -327,6 +327,28 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         else
             return s0 + gam * (S[k] * S[k]);
     };
+    // sigma_at() for a sweep that visits k = 0 .. R-1 in order (the set-up
+    // sweeps): with the sweep fully unrolled, S (the LDS stash in FP32
+    // tiles) is read a pinned group of cells at a time, at the group's
+    // first cell; read at each cell, every read was waited for before the
+    // next.
+    Real sgrp[kGroup];
+    auto sigma_seq = [&](int k) -> Real {
+        if constexpr (U == R) {
+            if (k % kGroup == 0) {
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j)
+                    sgrp[j] = k + j < R ? S[k + j] : Real(0);
+            }
+            const Real sk = sgrp[k % kGroup];
+            if constexpr (kSp == 0)
+                return s0 - gam * (hi[k] * sk);
+            else
+                return s0 + gam * (sk * sk);
+        } else {
+            return sigma_at(k);
+        }
+    };
     // sigma + 4c, the diagonal of the neighbour-sum form
     const Real s04 = uniform(s0 + Real(4) * c);
     auto sigma4_at = [&](int k) -> Real {
@@ -463,7 +485,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
                 for (int j = 0; j < kGroup; ++j)
                     h2g[j] = k + j < R ? h2[(k + j) * N] : Real(0);
             }
-            Real w = c * t + sigma_at(k) * own;  // (A H1) at the cell
+            Real w = c * t + sigma_seq(k) * own;  // (A H1) at the cell
             RD_PIN(w);
             const double wd = (double)w;
             g11 += (double)own * wd;
@@ -478,7 +500,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         __syncthreads();
         double g22 = 0.0, b2 = 0.0;
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
-            Real w = c * t + sigma_at(k) * own;  // (A H2) at the cell
+            Real w = c * t + sigma_seq(k) * own;  // (A H2) at the cell
             RD_PIN(w);
             g22 += (double)own * (double)w;
             b2 += (double)own * (double)r[k];
@@ -525,7 +547,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         }
         __syncthreads();
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
-            Real w = c * t + sigma_at(k) * own;  // (A d0) at the cell
+            Real w = c * t + sigma_seq(k) * own;  // (A d0) at the cell
             RD_PIN(w);
             r[k] = r[k] - w;
         });
@@ -541,7 +563,7 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         __syncthreads();
         double rw = 0.0, ww = 0.0;
         sweep<N, R, U>(P, g, [&](int k, Real own, Real t) {
-            Real w = c * t + sigma_at(k) * own;  // (A H) at the cell
+            Real w = c * t + sigma_seq(k) * own;  // (A H) at the cell
             RD_PIN(w);
             q[k] = w;
             rw += (double)r[k] * (double)w;
@@ -557,9 +579,19 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         ww = v4[3];
         quiet = !(rr > rtol2 * bb);
         const Real w = uniform((Real)((ww > 0.0 && finite(rw)) ? rw / ww : 0.0));
+        Real pg[kGroup];  // H's own cells, a group at a time (as in the CG loop)
 #pragma unroll U
         for (int k = 0; k < R; ++k) {
-            d[k] = w * P[g.idx(k)];
+            if constexpr (U == R) {
+                if (k % kGroup == 0) {
+#pragma unroll
+                    for (int j = 0; j < kGroup; ++j)
+                        pg[j] = k + j < R ? P[g.idx(k + j)] : Real(0);
+                }
+                d[k] = w * pg[k % kGroup];
+            } else {
+                d[k] = w * P[g.idx(k)];
+            }
             r[k] = r[k] - w * q[k];
             RD_GROUP_FENCE(k)
         }
@@ -656,13 +688,33 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
         }
         const Real bt = step_ratio<Real>(rn, rr);
         // d += alpha p_old and p = r + beta p_old (own cells only; the
-        // stencil reads of p finished before the p.q barrier).
+        // stencil reads of p finished before the p.q barrier).  Fully
+        // unrolled, the reads of a group of cells are issued together
+        // before its writes: read cell by cell, each read waited for the
+        // write before it (the compiler does not separate the cells'
+        // addresses), one LDS round trip per cell on every wave's path.
+        if constexpr (U == R) {
+            Real pg[kGroup];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                if (k % kGroup == 0) {
+#pragma unroll
+                    for (int j = 0; j < kGroup; ++j)
+                        pg[j] = k + j < R ? P[g.idx(k + j)] : Real(0);
+                }
+                const Real p = pg[k % kGroup];
+                d[k] = d[k] + a * p;
+                P[g.idx(k)] = r[k] + bt * p;
+                RD_GROUP_FENCE(k)
+            }
+        } else {
 #pragma unroll U
-        for (int k = 0; k < R; ++k) {
-            const Real p = P[g.idx(k)];
-            d[k] = d[k] + a * p;
-            P[g.idx(k)] = r[k] + bt * p;
-            RD_GROUP_FENCE(k)
+            for (int k = 0; k < R; ++k) {
+                const Real p = P[g.idx(k)];
+                d[k] = d[k] + a * p;
+                P[g.idx(k)] = r[k] + bt * p;
+                RD_GROUP_FENCE(k)
+            }
         }
         rr = rn;
     }
