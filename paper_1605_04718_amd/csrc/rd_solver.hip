@@ -1811,9 +1811,16 @@ __device__ int cg_coop(const RegArr<float, kCoopR> &hi, const LdsArr<float, kCoo
             break;
         }
         const float bt = step_ratio<float>(rn, rr);
+        static_assert(R % kGroup == 0, "whole groups");
+        float pg[kGroup];  // own cells of p, a group at a time (as in cg_solve)
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const float p = P[g.idx(k)];
+            if (k % kGroup == 0) {
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j)
+                    pg[j] = P[g.idx(k + j)];
+            }
+            const float p = pg[k % kGroup];
             d[k] = d[k] + a * p;
             P[g.idx(k)] = __builtin_fmaf(bt, p, r[k]);
             RD_GROUP_FENCE(k)
