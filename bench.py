@@ -93,12 +93,13 @@ FLOP_OVERHEAD_ITER = 3.0
 # timed step of `bench.py --steps 1 --warmup 0 --no-da --no-cpu-baseline
 # --no-mixed --no-stationary --no-config1 --no-loglik-error --legacy-steps 0`
 # at CG rtol 1e-9 (3831 solves, 29 438 831 completed solve-steps): FETCH_SIZE
-# 5 556 000 000 KiB x 2.00 + WRITE_SIZE 7 478 000 000 KiB x 1.00 (factors from a
+# 4 816 000 000 KiB x 2.00 + WRITE_SIZE 7 476 000 000 KiB x 1.00 (factors from a
 # 256 MiB copy), per completed solve-step.  Valid only for the kernel version
 # and tile it was measured on (step residual in FP64 below rtol 3e-8,
-# two-increment CG start with grouped history loads, row-summed workgroup
-# reductions; the queue order does not change what a solve reads or writes).
-MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 646634.4}
+# two-increment CG start, own-cell LDS and history reads grouped by four,
+# row-summed workgroup reductions, 112 B scratch per lane; the queue order does
+# not change what a solve reads or writes).
+MEASURED_TRAFFIC = {"k_solve_resident<128,16,float>": 595084.5}
 STATUS_BITS = ["not_converged", "breakdown", "nonfinite", "out_of_prior", "bad_grid",
                "not_steady", "group_timeout", "bit7"]
 GOLDEN = os.path.join(ROOT, "tests", "golden", "loglik_64.npz")
@@ -437,11 +438,23 @@ def stationary_leg(args, u0, v0, y, sigma, gold, log):
         # them; the Bonferroni bound at a 5 % family-wise level is beside it
         ncmp = 3 * len(pnames)
         zfw = float(_norm_ppf(1.0 - 0.025 / ncmp))
-        b["posterior_agreement_with_plain"] = {"max_diff_in_mcse": worst,
-                                               "matched_within_2_mcse": worst <= 2.0,
-                                               "familywise_5pct_bound_in_mcse": zfw,
-                                               "matched_familywise_5pct": worst <= zfw,
-                                               "per_parameter": agree}
+        # the MCSE behind these distances is only trustworthy when both
+        # samplers have mixed: with split-R-hat above the threshold the
+        # draws are short against the autocorrelation time, the MCSE is
+        # underestimated (tail quantiles most), and the test says little
+        rhs = [x["max_rhat"] for x in (ep, b)]
+        mixed_ok = all(r is not None and r <= args.st_rhat_ok for r in rhs)
+        agr = {"max_diff_in_mcse": worst,
+               "matched_within_2_mcse": worst <= 2.0,
+               "familywise_5pct_bound_in_mcse": zfw,
+               "matched_familywise_5pct": worst <= zfw,
+               "both_mixed": mixed_ok,
+               "per_parameter": agree}
+        if not mixed_ok:
+            agr["note"] = (f"split-R-hat {rhs[0]} (plain) and {rhs[1]} (this sampler): above "
+                           f"{args.st_rhat_ok} the MCSE is underestimated, so these distances "
+                           "are indicative only")
+        b["posterior_agreement_with_plain"] = agr
     blocks["da"]["surrogate_held_out"] = rep["held_out"]
     blocks["da"]["surrogate_fit_s"] = fit_s
     return {
