@@ -243,9 +243,6 @@ struct Slots {
 // FP32 rounding of its own terms, CG solves for the increment of the step
 // (a small quantity, well represented in FP32), and the increment is folded
 // back into hi + lo without loss.
-// Squared CG tolerance below which the resident FP32 solve evaluates its
-// step residual in FP64 (rtol < 3e-8: ten times the FP32 evaluation's
-// rounding floor relative to |b|).
 // The CG step lengths alpha = rr / pq and beta = rn / rr (FP64 sums) in
 // the working precision.  FP32 tiles take them from the hardware reciprocal
 // (within 1 ulp) times the numerator, about 1.5 ulp in all: the iteration
@@ -261,6 +258,9 @@ __device__ __forceinline__ Real step_ratio(double num, double den)
         return uniform(num / den);
 }
 
+// Squared CG tolerance below which the resident FP32 solve evaluates its
+// step residual in FP64 (rtol < 3e-8: ten times the FP32 evaluation's
+// rounding floor relative to |b|).
 constexpr double kRes64Rtol2 = 9e-16;
 
 template <typename Real>
@@ -312,6 +312,11 @@ __device__ int cg_solve(const Arr &hi, const SArr &S, Arr &r, Arr &q, Arr &d, Re
 {
     constexpr bool comp = Compensated<Real>::on;
     static_assert(!kFuse || (comp && kLds), "the fused set-up is for resident FP32 solves");
+    // the two-increment start reads the histories a group of kGroup cells at
+    // the group's first cell and indexes its group buffers with k % kGroup,
+    // a constant only when the unroll factor is a multiple of the group (the
+    // other grouped loops run only fully unrolled)
+    static_assert(!kPred2 || (U % kGroup == 0 && R % kGroup == 0), "unroll by whole groups");
     // e(k) and sigma(k) = 1/dt + e(k)
     const Real e0 = uniform(kSp == 0 ? dl + gam : dl);
     const Real s0 = uniform(e0 + inv_dt);
