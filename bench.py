@@ -19,6 +19,8 @@ Legs (each a block of the JSON line):
                the steps it finished), failures per status bit
   da           the same steps from the same chain states with a surrogate
                first stage trained on the library's own prior solves
+  plain_rtol_1e-7  the same chains at the earlier headline setting (CG rtol
+               1e-7, cap 400), for comparison with earlier measurements
   stationary   plain vs delayed acceptance near the posterior at a CG
                tolerance that resolves it: equal wall-clock budgets, ESS/s,
                split-R-hat, posterior means and 2.5/97.5 % quantiles compared
@@ -30,6 +32,10 @@ Legs (each a block of the JSON line):
                steps) on the GPU and on the FP64 oracle
   cpu_baseline the FP64 oracle on the host cores on a bounded sample of the
                128x128 workload
+
+The run keeps to --time-limit seconds from process start: the stationary
+budget shrinks and the legs after it are dropped (and listed in
+legs_skipped_for_time) rather than let the run overrun.
 """
 from __future__ import annotations
 
