@@ -101,9 +101,10 @@ typedef struct {
     int32_t n_steps;               /* T = dt * n_steps */
     double cg_rtol;                /* CG stop: ||r|| <= cg_rtol ||rhs|| */
     int32_t cg_maxit;              /* CG iteration cap per solve (<= 0: 10 n^2) */
-    int32_t precision;             /* RD_PRECISION_FP32: fields and CG vectors in
-                                      FP32, dot products, CG scalars and Phi in
-                                      FP64.  RD_PRECISION_FP64: everything FP64 */
+    int32_t precision;             /* RD_PRECISION_FP32: fields (as hi + lo) and CG
+                                      vectors in FP32, the CG step lengths in
+                                      FP32 from FP64 dot products, Phi in FP64.
+                                      RD_PRECISION_FP64: everything FP64 */
     uint32_t free_mask;            /* bit i set: sampling coordinate i moves */
     double lo[4], hi[4];           /* uniform prior box in sampling coordinates */
     double step[4];                /* random-walk proposal s.d. per coordinate */
